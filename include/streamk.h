@@ -1,0 +1,186 @@
+/*
+ * streamk.h -- C ABI of the MI355X (gfx950) Stream-K GEMM library.
+ *
+ * The library computes the GEMM of the paper's problem statement (section 2):
+ *     C = alpha * A * B + beta * C,   A: m x k,  B: k x n,  C: m x n
+ * with the work-centric Stream-K decomposition (section 4, Algorithm 5): a
+ * persistent grid of g workgroups splits the m->n->k linearised MAC-loop
+ * iteration space evenly, a workgroup may start or stop inside an output
+ * tile, and partial tiles are reconciled through a workspace with per-slot
+ * ready flags.  The data-parallel schedule (section 3.2, Algorithm 2) and the
+ * two hybrids of section 5.2 run in the same kernels.
+ *
+ * Conventions shared by every entry point:
+ *  - Only plain C types and pointers cross the boundary.  Device pointers are
+ *    HIP device addresses owned by the caller; `stream` is a hipStream_t
+ *    passed as void* (NULL = the null stream).  The library allocates no
+ *    device memory and keeps no mutable global state, so calls on distinct
+ *    workspaces may be issued from several host threads.
+ *  - Every entry point validates all arguments on the host before anything
+ *    is enqueued and returns an sk_status_t.  Compute entry points are
+ *    asynchronous: SK_OK means the work was enqueued on `stream`.
+ *  - Enumerations are passed as int32_t fields so the struct layout is fixed.
+ */
+#ifndef STREAMK_H
+#define STREAMK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SK_OK = 0,
+    SK_ERR_INVALID_VALUE = 1,      /* bad dimension, pointer, ld, scale, count */
+    SK_ERR_UNSUPPORTED = 2,        /* dtype / order / tile combination not built */
+    SK_ERR_WORKSPACE_TOO_SMALL = 3,
+    SK_ERR_MISALIGNED = 4,         /* see the alignment rule below */
+    SK_ERR_HIP = 5,                /* a HIP runtime call failed (no device, launch error) */
+    SK_ERR_TIMEOUT = 6             /* a fixup wait exceeded its bound (sk_workspace_check) */
+} sk_status_t;
+
+typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_order_t;
+
+/* F8_E4M3 is the OCP e4m3fn format (max 448, no infinities). */
+typedef enum { SK_F64 = 0, SK_F32 = 1, SK_F16 = 2, SK_BF16 = 3, SK_F8_E4M3 = 4 } sk_dtype_t;
+
+/* Work decompositions (paper sections 3.2, 4 and 5.2). */
+typedef enum {
+    SK_SCHED_AUTO = 0,          /* library default: two-tile SK + DP (the paper's evaluated kernel) */
+    SK_SCHED_DP = 1,            /* data-parallel: one workgroup per output tile (Algorithm 2) */
+    SK_SCHED_SK = 2,            /* basic Stream-K over all tiles (Algorithm 5), g from the model */
+    SK_SCHED_DP_1TILE_SK = 3,   /* full DP waves, then SK over the remaining tiles on g = p */
+    SK_SCHED_2TILE_SK_DP = 4    /* SK over r + p tiles first (1..2 tiles per WG), then DP waves */
+} sk_sched_t;
+
+/*
+ * One GEMM.  Element (i, j) of a rows x cols matrix X stored in order o with
+ * leading dimension ld (in elements) is X[i*ld + j] (row-major) or
+ * X[j*ld + i] (column-major).  ld == 0 means packed (cols resp. rows).
+ *
+ * Supported (ab_type -> c_type): F64 -> F64; F16 -> F32 | F16;
+ * BF16 -> BF16 | F32; F8_E4M3 -> BF16 | F32.  Products accumulate in FP32
+ * (FP64 for F64) and are never rounded to a narrower type before the final
+ * store.  alpha and beta are applied once, by the workgroup that writes the
+ * tile, in the accumulator precision; beta == 0 means C is not read.  For F8
+ * the stored codes are dequantised by the per-tensor scales:
+ *     C = alpha * (a_scale*A) * (b_scale*B) + beta * C;
+ * a_scale and b_scale must be finite and > 0 (and 1.0 for other dtypes).
+ *
+ * Alignment rule: A, B and C must be aligned to their element size and A
+ * and B to 16 bytes; for A and B, the leading dimension and the extent of the
+ * contiguous dimension (k for row-major A, m for column-major A, n for
+ * row-major B, k for column-major B) must be multiples of 16 bytes' worth of
+ * elements (8 for F16/BF16, 16 for F8, 2 for F64).  Otherwise SK_ERR_MISALIGNED.
+ * m == 0 or n == 0 is a no-op; k == 0 or alpha == 0 gives C = beta * C.
+ */
+typedef struct {
+    int64_t m, n, k;
+    double alpha, beta;
+    int32_t ab_type, c_type;              /* sk_dtype_t */
+    int32_t a_order, b_order, c_order;    /* sk_order_t */
+    int32_t reserved0;
+    int64_t lda, ldb, ldc;
+    const void *A;
+    const void *B;
+    void *C;
+    float a_scale, b_scale;
+} sk_gemm_desc_t;
+
+/*
+ * Launch configuration; every field 0 (or NULL) selects the library default.
+ *  sched            sk_sched_t.
+ *  blk_m/n/k        tile shape; must be one built for the dtype (see
+ *                   sk_plan for the default).  Built: F64 128x128x16, 64x64x16;
+ *                   F16/BF16 256x256x64, 128x128x64; F8 256x256x128, 128x128x128.
+ *  grid             g, the number of persistent workgroups (SK schedules).
+ *                   Must not exceed wg_slots: a fixup owner waits for
+ *                   higher-numbered workgroups, so all g must be co-resident.
+ *  wg_slots         p, resident workgroup slots (CUs x workgroups per CU for
+ *                   the chosen kernel); 0 = queried from the current device.
+ *  sk_threshold_waves  full waves w at and above which AUTO / 2TILE use the
+ *                   two-tile hybrid (below it, DP + one-tile SK); 0 = 2.
+ *  flags            SK_FLAG_* bits.
+ *  model_a..d       grid-size model constants of appendix A.1 (any unit);
+ *                   all zero = the library's calibrated constants.
+ *  trace            optional device buffer receiving one record per executed
+ *                   segment (for schedule verification); trace[0] is an
+ *                   int32 record counter the caller zeroes, records of 8
+ *                   int32 {wg, seq, tile, k_begin, k_end, role, last_peer, 0}
+ *                   start at trace[8].  Records beyond trace_capacity are
+ *                   dropped (the counter still counts them).
+ *                   role: 0 DP tile, 1 whole tile in one SK segment,
+ *                   2 owner (adds peers' partials), 3 producer (stores one).
+ */
+typedef struct {
+    int32_t sched;
+    int32_t blk_m, blk_n, blk_k;
+    int32_t grid;
+    int32_t wg_slots;
+    int32_t sk_threshold_waves;
+    int32_t flags;
+    double model_a, model_b, model_c, model_d;
+    int32_t *trace;
+    int64_t trace_capacity;
+} sk_config_t;
+
+#define SK_FLAG_NO_XCD_REMAP 0x1   /* keep logical workgroup id == hardware id */
+
+/* The resolved launch plan of a call (host only; no device access when
+ * cfg->wg_slots > 0). */
+typedef struct {
+    int32_t sched;            /* resolved schedule (never AUTO) */
+    int32_t blk_m, blk_n, blk_k;
+    int32_t grid;             /* workgroups launched */
+    int32_t wg_slots;         /* p used for the decision */
+    int32_t dp_first;         /* 1: each WG runs its DP tiles before its SK range */
+    int32_t xcd_remap;        /* 1: logical ids grouped per XCD */
+    int64_t tiles;            /* output tiles over all problems */
+    int64_t iters_total;      /* MAC-loop iterations over all problems */
+    int64_t sk_tile_begin, sk_tile_end;   /* SK region, in global tile order */
+    int64_t sk_iter_begin, sk_iters;      /* the same region in iterations */
+    int64_t dp_tiles;         /* tiles outside the SK region */
+    uint64_t workspace_bytes;
+} sk_plan_t;
+
+/* Plan the call without launching it.  d points to `count` descriptors
+ * (count == 1 for sk_gemm).  Pure host computation. */
+sk_status_t sk_plan(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg,
+                    sk_plan_t *out);
+
+/* Workspace bytes needed by sk_gemm (count == 1) or sk_gemm_grouped with the
+ * same descriptors and configuration.  The workspace is device memory owned
+ * by the caller; it must be zero-filled before its first use, and every call
+ * that completes leaves its flag region zeroed again.  One workspace serves
+ * one call in flight at a time. */
+sk_status_t sk_workspace_size(const sk_gemm_desc_t *d, int32_t count,
+                              const sk_config_t *cfg, size_t *bytes);
+
+/* One GEMM, enqueued on `stream`.  cfg may be NULL. */
+sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+/* `count` independent GEMMs with the same ab_type, c_type and orders but any
+ * shapes, pointers, alpha, beta and scales, in one persistent launch whose
+ * Stream-K iteration space is the concatenation of the problems' spaces
+ * (problem index outermost).  d is host memory; it is copied into the
+ * workspace stream-ordered, so it must stay valid until the stream reaches
+ * this call (pinned memory is required under stream capture, and replays of
+ * a captured call read d again: shapes must then be unchanged). */
+sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count,
+                            const sk_config_t *cfg, void *workspace,
+                            size_t ws_bytes, void *stream);
+
+/* Synchronise `stream`, read the workspace's error word and clear it.
+ * Returns SK_ERR_TIMEOUT if a fixup wait gave up since the last check. */
+sk_status_t sk_workspace_check(void *workspace, size_t ws_bytes, void *stream);
+
+/* Static text for a status code. */
+const char *sk_status_string(sk_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STREAMK_H */

@@ -26,7 +26,7 @@ notes with its reason):
 * the peers of an owner are the workgroups x+1 .. owner_of(last iteration of
   the tile) (Algorithm 5's loop bound yields a tile index, not a workgroup);
 * hybrids: with w = t // p full waves and r = t % p: r == 0 -> all tiles
-  data-parallel on g = p; w == 0 -> basic Stream-K with the model's g;
+  data-parallel on g = p (or the caller's grid); w == 0 -> basic Stream-K with the model's g;
   otherwise two-tile SK+DP when w >= threshold (default 2): SK over the first
   r + p tiles, then DP over the rest; else DP + one-tile SK: DP over the
   first w*p tiles, then SK over the last r tiles, g = p;
@@ -137,8 +137,9 @@ def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
     w, r = divmod(t, p)
     if r == 0:
         # perfect quantisation: full data-parallel waves on the whole machine
-        # (a hybrid whose Stream-K region is empty)
-        return Plan(p, 0, 0, True, SCHED_DP1, t, list(range(t)))
+        # (a hybrid whose Stream-K region is empty); a caller-given grid
+        # replaces p here as in every persistent schedule
+        return Plan(grid if grid > 0 else p, 0, 0, True, SCHED_DP1, t, list(range(t)))
     if w == 0:
         # no full wave: basic Stream-K with the model's grid size
         T = T_of_region(0, t)

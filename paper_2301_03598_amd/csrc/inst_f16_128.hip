@@ -1,0 +1,6 @@
+// Kernel instances: F16 inputs, 128x128 output tiles.
+#include "sk_dispatch.hpp"
+
+namespace sk {
+KernelEntry pick_f16_128(const KernelKey &k) { return pick<Dt::F16, 128, 128>(k); }
+}  // namespace sk

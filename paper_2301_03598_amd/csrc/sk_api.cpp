@@ -1,0 +1,482 @@
+// Host side of the C ABI: argument validation, the launch planner (tile,
+// schedule, grid size, Stream-K region) and the kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sk_internal.h"
+
+using namespace sk;
+
+namespace {
+
+struct TileDef {
+    int bm, bn, bk;
+};
+
+// Built tiles per input dtype; the first entry is the default.  The paper
+// keeps one tile per precision, the smallest that reaches its near-peak rate
+// on very large problems (section 5.1); the second entry serves the
+// autotuner and the data-parallel ensemble comparison.
+const TileDef kF64Tiles[] = {{128, 128, 16}, {64, 64, 16}};
+const TileDef k16Tiles[] = {{256, 256, 64}, {128, 128, 64}};
+const TileDef kF8Tiles[] = {{256, 256, 128}, {128, 128, 128}};
+
+const TileDef *tiles_for(int ab, int *n) {
+    *n = 2;
+    switch (ab) {
+    case SK_F64: return kF64Tiles;
+    case SK_F16:
+    case SK_BF16: return k16Tiles;
+    case SK_F8_E4M3: return kF8Tiles;
+    }
+    *n = 0;
+    return nullptr;
+}
+
+// Appendix A.1 grid-size model constants {a, b, c, d} in microseconds:
+// a fixed per-workgroup cost, b the cost of emitting a partial tile, c one
+// MAC-loop iteration, d reading and adding one peer's partial tile.
+struct Model {
+    double a, b, c, d;
+};
+
+Model default_model(int ab, int bm) {
+    // c: one iteration at the dtype's dense MFMA rate on one CU (2.4 GHz);
+    // b, d: one partial tile (BM*BN accumulators) written resp. read and
+    // added at an assumed ~100 GB/s per CU.
+    double flops_per_cu = ab == SK_F64 ? 78.6e12 / 256 : ab == SK_F8_E4M3 ? 5033e12 / 256 : 2516.6e12 / 256;
+    int bk = ab == SK_F64 ? 16 : ab == SK_F8_E4M3 ? 128 : 64;
+    double c = 2.0 * bm * bm * bk / flops_per_cu * 1e6;
+    double tile_bytes = (double)bm * bm * (ab == SK_F64 ? 8 : 4);
+    double bd = tile_bytes / 100e9 * 1e6;
+    return Model{2.0, bd, c, bd};
+}
+
+bool supported_pair(int ab, int c) {
+    switch (ab) {
+    case SK_F64: return c == SK_F64;
+    case SK_F16: return c == SK_F32 || c == SK_F16;
+    case SK_BF16: return c == SK_BF16 || c == SK_F32;
+    case SK_F8_E4M3: return c == SK_BF16 || c == SK_F32;
+    }
+    return false;
+}
+
+bool is_order(int o) { return o == SK_ROW_MAJOR || o == SK_COL_MAJOR; }
+
+sk_status_t validate(const sk_gemm_desc_t &d) {
+    if (d.m < 0 || d.n < 0 || d.k < 0) return SK_ERR_INVALID_VALUE;
+    if (d.m > (1LL << 30) || d.n > (1LL << 30) || d.k > (1LL << 30)) return SK_ERR_INVALID_VALUE;
+    if (!is_order(d.a_order) || !is_order(d.b_order) || !is_order(d.c_order)) return SK_ERR_INVALID_VALUE;
+    if (d.ab_type < SK_F64 || d.ab_type > SK_F8_E4M3 || d.c_type < SK_F64 || d.c_type > SK_F8_E4M3)
+        return SK_ERR_INVALID_VALUE;
+    if (!supported_pair(d.ab_type, d.c_type)) return SK_ERR_UNSUPPORTED;
+    if (d.ab_type == SK_F8_E4M3) {
+        if (!(std::isfinite(d.a_scale) && d.a_scale > 0.0f && std::isfinite(d.b_scale) && d.b_scale > 0.0f))
+            return SK_ERR_INVALID_VALUE;
+    } else if (!((d.a_scale == 0.0f || d.a_scale == 1.0f) && (d.b_scale == 0.0f || d.b_scale == 1.0f))) {
+        return SK_ERR_INVALID_VALUE;
+    }
+    if (d.lda < 0 || d.ldb < 0 || d.ldc < 0) return SK_ERR_INVALID_VALUE;
+    if (d.m == 0 || d.n == 0) return SK_OK;
+    // leading dimensions cover the packed extent
+    const int64_t a_ext = d.a_order == SK_ROW_MAJOR ? d.k : d.m;
+    const int64_t b_ext = d.b_order == SK_ROW_MAJOR ? d.n : d.k;
+    const int64_t c_ext = d.c_order == SK_ROW_MAJOR ? d.n : d.m;
+    if (d.ldc != 0 && d.ldc < c_ext) return SK_ERR_INVALID_VALUE;
+    if (!d.C) return SK_ERR_INVALID_VALUE;
+    if (((uintptr_t)d.C) % (uintptr_t)dtype_bytes(d.c_type)) return SK_ERR_MISALIGNED;
+    if (d.k == 0 || d.alpha == 0.0) return SK_OK;   // A and B are not referenced
+    if (d.lda != 0 && d.lda < a_ext) return SK_ERR_INVALID_VALUE;
+    if (d.ldb != 0 && d.ldb < b_ext) return SK_ERR_INVALID_VALUE;
+    if (!d.A || !d.B) return SK_ERR_INVALID_VALUE;
+    const int vec = 16 / dtype_bytes(d.ab_type);
+    const int64_t lda = d.lda ? d.lda : a_ext, ldb = d.ldb ? d.ldb : b_ext;
+    if (((uintptr_t)d.A & 15u) || ((uintptr_t)d.B & 15u)) return SK_ERR_MISALIGNED;
+    if (lda % vec || ldb % vec || a_ext % vec || b_ext % vec) return SK_ERR_MISALIGNED;
+    return SK_OK;
+}
+
+sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
+    int n = 0;
+    const TileDef *t = tiles_for(ab, &n);
+    if (!t) return SK_ERR_UNSUPPORTED;
+    if (!cfg || (cfg->blk_m == 0 && cfg->blk_n == 0 && cfg->blk_k == 0)) {
+        *out = t[0];
+        return SK_OK;
+    }
+    for (int i = 0; i < n; ++i)
+        if (t[i].bm == cfg->blk_m && t[i].bn == cfg->blk_n && (cfg->blk_k == 0 || t[i].bk == cfg->blk_k)) {
+            *out = t[i];
+            return SK_OK;
+        }
+    return SK_ERR_UNSUPPORTED;
+}
+
+// Resident workgroup slots of a kernel on the current device (cached).
+struct SlotKey {
+    int dev, ab, bm;
+    bool akc, bkc, grouped;
+    bool operator==(const SlotKey &o) const {
+        return dev == o.dev && ab == o.ab && bm == o.bm && akc == o.akc && bkc == o.bkc && grouped == o.grouped;
+    }
+};
+std::mutex g_slot_mu;
+std::vector<std::pair<SlotKey, int>> g_slot_cache;
+
+sk_status_t query_slots(const KernelKey &key, int *slots) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+    SlotKey sk_{dev, key.ab_type, key.bm, key.a_kc, key.b_kc, key.grouped};
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        for (auto &e : g_slot_cache)
+            if (e.first == sk_) {
+                *slots = e.second;
+                return SK_OK;
+            }
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return SK_ERR_HIP;
+    KernelKey k2 = key;
+    k2.dp_only = false;
+    KernelEntry e = find_kernel(k2);
+    if (!e.occupancy) return SK_ERR_UNSUPPORTED;
+    int bpc = 0;
+    if (e.occupancy(&bpc) != (int)hipSuccess || bpc <= 0) return SK_ERR_HIP;
+    *slots = cus * bpc;
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_slot_cache.push_back({sk_, *slots});
+    return SK_OK;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Appendix A.1: g* = argmin over g in [1, min(p, T)] of
+//   a + b [peers > 1] + c ItersPerCta(g) + d (peers - 1),
+// ItersPerCta(g) = ceil(T / g), peers = ceil(I / ItersPerCta(g)); ties take
+// the smallest g.
+int model_grid(int64_t T, int64_t I, int p, const Model &m) {
+    int best_g = 1;
+    double best = 0.0;
+    const int64_t gmax = std::max<int64_t>(1, std::min<int64_t>(p, T));
+    for (int64_t g = 1; g <= gmax; ++g) {
+        const int64_t ipc = cdiv(T, g);
+        const int64_t peers = cdiv(I, ipc);
+        const double v = m.a + m.b * (peers > 1 ? 1.0 : 0.0) + m.c * (double)ipc + m.d * (double)(peers - 1);
+        if (g == 1 || v < best) {
+            best = v;
+            best_g = (int)g;
+        }
+    }
+    return best_g;
+}
+
+// Host view of one call: problems (kernel form), tile, key and prefix sums.
+struct Call {
+    std::vector<Problem> probs;
+    std::vector<int64_t> tile_prefix, iter_prefix;   // count + 1
+    TileDef tile;
+    KernelKey key;
+    int64_t tiles = 0, iters = 0, imax = 0;
+
+    int64_t tile_iter_begin(int64_t tile_g) const {
+        // problem holding tile_g (last index with prefix <= tile_g)
+        size_t lo = 0, hi = probs.size();
+        while (hi - lo > 1) {
+            size_t mid = (lo + hi) / 2;
+            if (tile_prefix[mid] <= tile_g) lo = mid; else hi = mid;
+        }
+        return iter_prefix[lo] + (tile_g - tile_prefix[lo]) * probs[lo].iters;
+    }
+    int64_t region_iters(int64_t tb, int64_t te) const {
+        if (te <= tb) return 0;
+        return (te >= tiles ? iters : tile_iter_begin(te)) - tile_iter_begin(tb);
+    }
+};
+
+sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, bool grouped,
+                       Call *c) {
+    if (!d || count <= 0) return SK_ERR_INVALID_VALUE;
+    for (int i = 0; i < count; ++i) {
+        sk_status_t s = validate(d[i]);
+        if (s != SK_OK) return s;
+        if (grouped) {
+            if (d[i].ab_type != d[0].ab_type || d[i].c_type != d[0].c_type || d[i].a_order != d[0].a_order ||
+                d[i].b_order != d[0].b_order || d[i].c_order != d[0].c_order)
+                return SK_ERR_UNSUPPORTED;
+            if (d[i].m > 0 && d[i].n > 0 && d[i].k == 0) return SK_ERR_UNSUPPORTED;
+        }
+    }
+    sk_status_t s = resolve_tile(d[0].ab_type, cfg, &c->tile);
+    if (s != SK_OK) return s;
+    c->key = KernelKey{d[0].ab_type, c->tile.bm, c->tile.bn, a_kcontig(d[0]), b_kcontig(d[0]), grouped, false};
+    c->probs.resize(count);
+    c->tile_prefix.assign(count + 1, 0);
+    c->iter_prefix.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        Problem p = to_problem(d[i], c->tile.bm, c->tile.bn, c->tile.bk);
+        c->probs[i] = p;
+        const int64_t t = (p.m > 0 && p.n > 0) ? cdiv(p.m, c->tile.bm) * (int64_t)p.tiles_n : 0;
+        c->tile_prefix[i + 1] = c->tile_prefix[i] + t;
+        c->iter_prefix[i + 1] = c->iter_prefix[i] + t * p.iters;
+        if (t > 0) c->imax = std::max<int64_t>(c->imax, p.iters);
+    }
+    c->tiles = c->tile_prefix[count];
+    c->iters = c->iter_prefix[count];
+    if (c->tiles >= (1LL << 31) || c->iters >= (1LL << 31)) return SK_ERR_INVALID_VALUE;
+    return SK_OK;
+}
+
+// The schedule: which tiles form the Stream-K region and how many
+// workgroups run.  Section 5.2 hybrids with w = t / p full waves, r = t % p:
+//  r == 0           -> whole waves of data-parallel tiles on g = p;
+//  w == 0           -> basic Stream-K over every tile with the model's g;
+//  two-tile SK + DP -> (w >= threshold) SK over the first r + p tiles, each
+//                      workgroup getting 1..2 tiles of iterations, then DP;
+//  DP + one-tile SK -> DP over the first w*p tiles, then SK over the last r.
+sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
+    std::memset(pl, 0, sizeof(*pl));
+    pl->blk_m = c.tile.bm;
+    pl->blk_n = c.tile.bn;
+    pl->blk_k = c.tile.bk;
+    pl->tiles = c.tiles;
+    pl->iters_total = c.iters;
+    int sched = cfg ? cfg->sched : SK_SCHED_AUTO;
+    if (sched < SK_SCHED_AUTO || sched > SK_SCHED_2TILE_SK_DP) return SK_ERR_INVALID_VALUE;
+    const int user_grid = cfg ? cfg->grid : 0;
+    if (user_grid < 0) return SK_ERR_INVALID_VALUE;
+    const int threshold = (cfg && cfg->sk_threshold_waves > 0) ? cfg->sk_threshold_waves : 2;
+    Model mc = default_model(c.key.ab_type, c.tile.bm);
+    if (cfg && (cfg->model_a != 0.0 || cfg->model_b != 0.0 || cfg->model_c != 0.0 || cfg->model_d != 0.0))
+        mc = Model{cfg->model_a, cfg->model_b, cfg->model_c, cfg->model_d};
+    const int64_t t = c.tiles;
+    pl->xcd_remap = (cfg && (cfg->flags & SK_FLAG_NO_XCD_REMAP)) ? 0 : 1;
+    if (t == 0) {
+        pl->sched = sched == SK_SCHED_AUTO ? SK_SCHED_2TILE_SK_DP : sched;
+        return SK_OK;
+    }
+    if (sched == SK_SCHED_DP) {
+        pl->sched = SK_SCHED_DP;
+        pl->grid = (int32_t)t;
+        pl->dp_first = 1;
+        pl->dp_tiles = t;
+        pl->xcd_remap = 0;
+        return SK_OK;
+    }
+    int p = cfg ? cfg->wg_slots : 0;
+    if (p < 0) return SK_ERR_INVALID_VALUE;
+    if (p == 0) {
+        sk_status_t s = query_slots(c.key, &p);
+        if (s != SK_OK) return s;
+    }
+    pl->wg_slots = p;
+    if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
+    if (sched == SK_SCHED_AUTO) sched = SK_SCHED_2TILE_SK_DP;
+    const int64_t w = t / p, r = t % p;
+    int64_t skb = 0, ske = 0;
+    int64_t g = 0;
+    if (sched == SK_SCHED_SK || (w == 0 && r != 0)) {
+        sched = SK_SCHED_SK;
+        skb = 0;
+        ske = t;
+        g = user_grid > 0 ? user_grid : model_grid(c.iters, c.imax, p, mc);
+    } else if (r == 0) {
+        // perfect quantisation: data-parallel waves only
+        sched = SK_SCHED_DP_1TILE_SK;
+        skb = ske = 0;
+        g = user_grid > 0 ? user_grid : p;
+    } else if (sched == SK_SCHED_2TILE_SK_DP && w >= threshold) {
+        skb = 0;
+        ske = r + p;
+        g = user_grid > 0 ? user_grid : p;
+    } else {
+        sched = SK_SCHED_DP_1TILE_SK;
+        skb = w * p;
+        ske = t;
+        g = user_grid > 0 ? user_grid : p;
+    }
+    const int64_t sk_iters = c.region_iters(skb, ske);
+    if (sk_iters > 0) g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
+    pl->sched = sched;
+    pl->grid = (int32_t)g;
+    pl->dp_first = sched == SK_SCHED_DP_1TILE_SK ? 1 : 0;
+    pl->sk_tile_begin = skb;
+    pl->sk_tile_end = ske;
+    pl->sk_iter_begin = skb < t ? c.tile_iter_begin(skb) : c.iters;
+    pl->sk_iters = sk_iters;
+    pl->dp_tiles = t - (ske - skb);
+    return SK_OK;
+}
+
+struct Layout {
+    size_t flags = 0, partials = 0, raw = 0, probs = 0, tpre = 0, ipre = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout_for(const sk_plan_t &pl, int ab, int32_t count, bool grouped) {
+    Layout L;
+    size_t off = WS_HEADER;
+    if (pl.sched != SK_SCHED_DP && pl.grid > 0) {
+        L.flags = off;
+        off = align256(off + (size_t)pl.grid * FLAG_STRIDE * sizeof(int32_t));
+        L.partials = off;
+        const size_t acc = ab == SK_F64 ? 8 : 4;
+        off = align256(off + (size_t)pl.grid * pl.blk_m * pl.blk_n * acc);
+    }
+    if (grouped) {
+        L.raw = off;
+        off = align256(off + (size_t)count * sizeof(sk_gemm_desc_t));
+        L.probs = off;
+        off = align256(off + (size_t)count * sizeof(Problem));
+        L.tpre = off;
+        off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
+        L.ipre = off;
+        off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
+    }
+    L.total = off;
+    return L;
+}
+
+constexpr int kSpinLimit = 1 << 22;
+
+Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws,
+                   const sk_config_t *cfg) {
+    Params P;
+    std::memset(&P, 0, sizeof(P));
+    P.prob = c.probs[0];
+    P.tiles = (int32_t)c.tiles;
+    P.g = pl.grid;
+    P.sk_tile_begin = (int32_t)pl.sk_tile_begin;
+    P.sk_tile_end = (int32_t)pl.sk_tile_end;
+    P.sk_iter_begin = (int32_t)pl.sk_iter_begin;
+    P.sk_iters = (int32_t)pl.sk_iters;
+    P.dp_tiles = (int32_t)pl.dp_tiles;
+    P.dp_first = pl.dp_first;
+    P.xcd_remap = pl.xcd_remap;
+    P.spin_limit = kSpinLimit;
+    char *w = (char *)ws;
+    P.err = (int32_t *)w;
+    if (L.flags) P.flags = (int32_t *)(w + L.flags);
+    if (L.partials) P.partials = w + L.partials;
+    if (cfg && cfg->trace) {
+        P.trace = cfg->trace;
+        P.trace_cap = cfg->trace_capacity;
+    }
+    return P;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sk_status_string(sk_status_t s) {
+    switch (s) {
+    case SK_OK: return "SK_OK";
+    case SK_ERR_INVALID_VALUE: return "SK_ERR_INVALID_VALUE";
+    case SK_ERR_UNSUPPORTED: return "SK_ERR_UNSUPPORTED";
+    case SK_ERR_WORKSPACE_TOO_SMALL: return "SK_ERR_WORKSPACE_TOO_SMALL";
+    case SK_ERR_MISALIGNED: return "SK_ERR_MISALIGNED";
+    case SK_ERR_HIP: return "SK_ERR_HIP";
+    case SK_ERR_TIMEOUT: return "SK_ERR_TIMEOUT";
+    }
+    return "SK_ERR_UNKNOWN";
+}
+
+sk_status_t sk_plan(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, sk_plan_t *out) {
+    if (!out) return SK_ERR_INVALID_VALUE;
+    Call c;
+    sk_status_t s = build_call(d, count, cfg, count > 1, &c);
+    if (s != SK_OK) return s;
+    s = plan_call(c, cfg, out);
+    if (s != SK_OK) return s;
+    out->workspace_bytes = layout_for(*out, d[0].ab_type, count, count > 1).total;
+    return SK_OK;
+}
+
+sk_status_t sk_workspace_size(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, size_t *bytes) {
+    if (!bytes) return SK_ERR_INVALID_VALUE;
+    sk_plan_t pl;
+    sk_status_t s = sk_plan(d, count, cfg, &pl);
+    if (s != SK_OK) return s;
+    *bytes = (size_t)pl.workspace_bytes;
+    return SK_OK;
+}
+
+sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *workspace, size_t ws_bytes,
+                    void *stream) {
+    if (!d) return SK_ERR_INVALID_VALUE;
+    sk_status_t s = validate(*d);
+    if (s != SK_OK) return s;
+    if (d->m == 0 || d->n == 0) return SK_OK;
+    if (d->k == 0 || d->alpha == 0.0) {
+        Problem p = to_problem(*d, 1, 1, 1);
+        return launch_scale_c(p, stream) == (int)hipSuccess ? SK_OK : SK_ERR_HIP;
+    }
+    Call c;
+    s = build_call(d, 1, cfg, false, &c);
+    if (s != SK_OK) return s;
+    sk_plan_t pl;
+    s = plan_call(c, cfg, &pl);
+    if (s != SK_OK) return s;
+    Layout L = layout_for(pl, d->ab_type, 1, false);
+    if (!workspace || ws_bytes < L.total) return SK_ERR_WORKSPACE_TOO_SMALL;
+    KernelKey key = c.key;
+    key.dp_only = pl.sched == SK_SCHED_DP;
+    KernelEntry e = find_kernel(key);
+    if (!e.launch) return SK_ERR_UNSUPPORTED;
+    Params P = make_params(c, pl, L, workspace, cfg);
+    return e.launch(P, pl.grid, stream) == (int)hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, void *workspace,
+                            size_t ws_bytes, void *stream) {
+    Call c;
+    sk_status_t s = build_call(d, count, cfg, true, &c);
+    if (s != SK_OK) return s;
+    sk_plan_t pl;
+    s = plan_call(c, cfg, &pl);
+    if (s != SK_OK) return s;
+    Layout L = layout_for(pl, d[0].ab_type, count, true);
+    if (!workspace || ws_bytes < L.total) return SK_ERR_WORKSPACE_TOO_SMALL;
+    if (c.tiles == 0) return SK_OK;
+    KernelKey key = c.key;
+    key.dp_only = pl.sched == SK_SCHED_DP;
+    KernelEntry e = find_kernel(key);
+    if (!e.launch) return SK_ERR_UNSUPPORTED;
+    char *w = (char *)workspace;
+    if (hipMemcpyAsync(w + L.raw, d, sizeof(sk_gemm_desc_t) * (size_t)count, hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess)
+        return SK_ERR_HIP;
+    GroupTable tab;
+    tab.probs = (Problem *)(w + L.probs);
+    tab.tile_prefix = (int32_t *)(w + L.tpre);
+    tab.iter_prefix = (int32_t *)(w + L.ipre);
+    tab.count = count;
+    if (launch_group_prep((const sk_gemm_desc_t *)(w + L.raw), count, c.tile.bm, c.tile.bn, c.tile.bk, tab,
+                          stream) != (int)hipSuccess)
+        return SK_ERR_HIP;
+    Params P = make_params(c, pl, L, workspace, cfg);
+    P.group = tab;
+    return e.launch(P, pl.grid, stream) == (int)hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+sk_status_t sk_workspace_check(void *workspace, size_t ws_bytes, void *stream) {
+    if (!workspace || ws_bytes < (size_t)WS_HEADER) return SK_ERR_INVALID_VALUE;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SK_ERR_HIP;
+    int32_t err = 0;
+    if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return SK_ERR_HIP;
+    if (err == 0) return SK_OK;
+    const int32_t zero = 0;
+    if (hipMemcpy(workspace, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return SK_ERR_HIP;
+    return SK_ERR_TIMEOUT;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""Helpers for the GPU parity tests: run the library through the C ABI on
+seeded inputs and compare with the CPU oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+import workloads as W
+from oracle import schedule as O
+from paper_2301_03598_amd import runtime as R
+from paper_2301_03598_amd import streamk as S
+
+F64_BOUND = 1e-13           # normwise, FP64
+LOWP_BOUND = 5e-5           # normwise, FP16/BF16/FP8 with FP32 accumulation (k <= 65536)
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(op: W.Operand) -> W.Operand:
+    return op.to("cuda")
+
+
+def c_tensor(m, n, c_type, c_order, init: np.ndarray | None = None):
+    """Device C in its storage order (logical m x n) and its ld."""
+    if init is None:
+        logical = torch.full((m, n), float("nan"), dtype=torch.float64)
+    else:
+        logical = torch.from_numpy(np.ascontiguousarray(init))
+    t = logical.to(W.torch_dtype(c_type))
+    if c_order == "row":
+        return t.contiguous().cuda(), n
+    return t.t().contiguous().cuda(), m
+
+
+def c_logical(Ct: torch.Tensor, m, n, c_order) -> torch.Tensor:
+    h = Ct.cpu()
+    return h if c_order == "row" else h.t()
+
+
+def c_values(Ct, m, n, c_order) -> np.ndarray:
+    return c_logical(Ct, m, n, c_order).double().numpy()
+
+
+def c_bits(Ct, m, n, c_order) -> np.ndarray:
+    h = c_logical(Ct, m, n, c_order).contiguous()
+    if h.dtype == torch.float64:
+        return h.view(torch.int64).numpy()
+    if h.dtype == torch.float32:
+        return h.view(torch.int32).numpy().view(np.uint32)
+    return h.view(torch.int16).numpy().view(np.uint16)
+
+
+def expected_bits(cref: np.ndarray, c_type: str) -> np.ndarray:
+    if c_type == "f64":
+        return np.ascontiguousarray(cref).view(np.int64)
+    return oracle.round_to(cref, c_type)
+
+
+def rel_err(C: np.ndarray, Cref: np.ndarray, Ad: np.ndarray, Bd: np.ndarray) -> float:
+    den = np.linalg.norm(Ad) * np.linalg.norm(Bd)
+    return float(np.linalg.norm(C - Cref) / den) if den > 0 else float(np.linalg.norm(C - Cref))
+
+
+def bound_for(ab_type: str, c_type: str, cref, Ad, Bd) -> float:
+    if ab_type == "f64":
+        return F64_BOUND
+    b = LOWP_BOUND
+    if c_type in ("bf16", "f16"):
+        # the output's own rounding is allowed on top (one rounding of Cref)
+        rounded = oracle.decode(oracle.round_to(cref, c_type), c_type)
+        b += rel_err(rounded, cref, Ad, Bd)
+    return b
+
+
+def run_gemm(m, n, k, A, B, *, c_type, c_order="row", C0=None, alpha=1.0, beta=0.0, cfg=None,
+             ws=None, trace_cap=0):
+    """Launch sk_gemm on device operands; returns (C tensor, plan, trace)."""
+    Ct, ldc = c_tensor(m, n, c_type, c_order, C0)
+    tr = None
+    if trace_cap:
+        tr = torch.zeros(8 + 8 * trace_cap, dtype=torch.int32, device="cuda")
+        cfg = cfg or S.make_config()
+        cfg.trace = tr.data_ptr()
+        cfg.trace_capacity = trace_cap
+    ws = ws or R.Workspace("cuda")
+    plan = R.gemm(m, n, k, A, B, Ct, c_type=c_type, c_order=c_order, ldc=ldc, alpha=alpha,
+                  beta=beta, cfg=cfg, ws=ws)
+    torch.cuda.synchronize()
+    ws.check()
+    trace = R.read_trace(tr) if tr is not None else None
+    return Ct, plan, trace
+
+
+def oracle_segments(plan, shapes, c_order="row"):
+    """Per-WG segment lists the schedule oracle predicts for a library plan."""
+    blk = (plan.blk_m, plan.blk_n, plan.blk_k)
+    oshapes = [(n, m, k) if c_order == "col" else (m, n, k) for (m, n, k) in shapes]
+    geos = [O.geometry(m, n, k, *blk) for (m, n, k) in oshapes]
+    probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, oshapes)])
+    op = O.Plan(plan.grid, plan.sk_tile_begin, plan.sk_tile_end, bool(plan.dp_first), plan.sched,
+                probs.tiles,
+                [t for t in range(probs.tiles) if not (plan.sk_tile_begin <= t < plan.sk_tile_end)])
+    segs = O.segments(probs, op)
+    O.check_invariants(probs, op, segs)
+    return segs
+
+
+def compare_trace(trace, plan, shapes, c_order="row"):
+    count, recs = trace
+    segs = oracle_segments(plan, shapes, c_order)
+    expect = sum(len(l) for l in segs)
+    assert count == expect, f"trace has {count} records, oracle {expect}"
+    got = {}
+    for (wg, seq, tile, k0, k1, role, last) in recs:
+        got.setdefault(wg, []).append((seq, tile, k0, k1, role, last))
+    for x, lst in enumerate(segs):
+        mine = [r[1:] for r in sorted(got.get(x, []))]
+        want = [(s.tile, s.k_begin, s.k_end, s.role, s.peers[-1] if s.peers else -1) for s in lst]
+        assert mine == want, f"workgroup {x}: {mine[:4]} != {want[:4]}"

@@ -1,0 +1,197 @@
+"""GPU parity of the Stream-K library against the CPU oracle, through the C ABI.
+
+Integer-valued inputs (entries in {-4..4}) make every partial sum exact in
+FP32 and FP64, so results must match the oracle bit for bit for every
+schedule, grid and operand layout (the oracle's exact value rounded once to
+the output type).  Real-valued inputs must meet the normwise bound
+||C - Cref||_F / (||A||_F ||B||_F) <= 1e-13 (FP64) or 5e-5 (FP32
+accumulation), measured against the oracle on the stored (rounded or
+dequantised) inputs.  Traces of the executed segments must equal the
+schedule oracle's segment lists, and reruns must be bitwise identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2301_03598_amd import runtime as R
+from paper_2301_03598_amd import streamk as S
+from tests.gpu_util import (bound_for, c_bits, c_values, compare_trace, dev, expected_bits,
+                            rel_err, run_gemm, say)
+
+pytestmark = pytest.mark.gpu
+
+PAIRS = [("f64", "f64"), ("f16", "f32"), ("f16", "f16"), ("bf16", "bf16"), ("bf16", "f32"),
+         ("f8e4m3", "bf16"), ("f8e4m3", "f32")]
+SMALL_TILE = {"f64": (64, 64, 16), "f16": (128, 128, 64), "bf16": (128, 128, 64),
+              "f8e4m3": (128, 128, 128)}
+BIG_TILE = {"f64": (128, 128, 16), "f16": (256, 256, 64), "bf16": (256, 256, 64),
+            "f8e4m3": (256, 256, 128)}
+
+
+@pytest.fixture(scope="module")
+def ws():
+    return R.Workspace("cuda")
+
+
+def operands(m, n, k, dtype, seed, dist, a_order="row", b_order="row", scale=None):
+    if dtype == "f8e4m3" and dist == "int4":
+        scale = 1.0
+    A, B = W.gemm_operands(m, n, k, dtype, seed, dist, a_order, b_order, fp8_scale=scale)
+    return A, B
+
+
+def check_case(m, n, k, ab, ct, *, dist, seed=0, a_order="row", b_order="row", c_order="row",
+               cfg=None, alpha=1.0, beta=0.0, ws=None, trace=True):
+    say(f"case m={m} n={n} k={k} {ab}->{ct} {a_order}/{b_order}/{c_order} {dist} "
+        f"alpha={alpha} beta={beta} sched={cfg.sched if cfg else 0} grid={cfg.grid if cfg else 0}")
+    A, B = operands(m, n, k, ab, seed, dist, a_order, b_order)
+    C0 = None
+    Cop = None
+    if beta != 0.0:
+        rng = np.random.default_rng(seed + 99)
+        C0 = W.small_integers((m, n), rng) if dist == "int4" else W.uniform((m, n), rng)
+        Cop = W.store(C0, ct, c_order)
+        C0 = oracle.decode_operand(Cop)          # the exact stored C values
+    Ct, plan, tr = run_gemm(m, n, k, dev(A), dev(B), c_type=ct, c_order=c_order, C0=C0, alpha=alpha,
+                            beta=beta, cfg=cfg, ws=ws, trace_cap=4096 if trace else 0)
+    cref = oracle.gemm(m, n, k, A, B, Cop, alpha=alpha, beta=beta, c_type=ct)
+    if dist == "int4":
+        got = c_bits(Ct, m, n, c_order)
+        want = expected_bits(cref, ct)
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[0]}: " \
+                              f"{c_values(Ct, m, n, c_order)[tuple(bad[0])]} vs {cref[tuple(bad[0])]}"
+    else:
+        Ad, Bd = oracle.decode_operand(A), oracle.decode_operand(B)
+        err = rel_err(c_values(Ct, m, n, c_order), cref, Ad, Bd)
+        bound = bound_for(ab, ct, cref, Ad, Bd)
+        say(f"  rel err {err:.3e} (bound {bound:.3e})")
+        assert err <= bound
+    if tr is not None:
+        compare_trace(tr, plan, [(m, n, k)], c_order)
+    return Ct, plan
+
+
+# ---------------------------------------------------------------- config 1
+
+CFG1 = (384, 384, 1024)
+
+
+@pytest.mark.parametrize("grid", [9, 16, 64, 256, 0])
+@pytest.mark.parametrize("dist", ["int4", "uniform"])
+def test_config1_fp64_streamk_grids(grid, dist, ws):
+    m, n, k = CFG1
+    cfg = S.make_config(sched="sk", blk=(128, 128, 16), grid=grid)
+    Ct, plan = check_case(m, n, k, "f64", "f64", dist=dist, cfg=cfg, ws=ws)
+    assert plan.tiles == 9 and plan.iters_total == 576
+    if grid:
+        assert plan.grid == grid
+    # reruns are bitwise identical (fixed fixup order)
+    cfg2 = S.make_config(sched="sk", blk=(128, 128, 16), grid=grid)
+    Ct2, _ = check_case(m, n, k, "f64", "f64", dist=dist, cfg=cfg2, ws=ws, trace=False)
+    assert torch.equal(Ct.view(torch.int64), Ct2.view(torch.int64))
+
+
+def test_streamk_with_g_equal_tiles_is_data_parallel(ws):
+    m, n, k = CFG1
+    A, B = operands(m, n, k, "f64", 0, "uniform")
+    outs = []
+    for cfg in (S.make_config(sched="sk", blk=(128, 128, 16), grid=9),
+                S.make_config(sched="dp", blk=(128, 128, 16))):
+        Ct, plan, _ = run_gemm(m, n, k, dev(A), dev(B), c_type="f64", cfg=cfg, ws=ws)
+        outs.append(Ct.view(torch.int64).cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------- dtypes x layouts x schedules
+
+RAGGED = (208, 336, 400)     # not multiples of any tile; multiples of 16
+
+
+@pytest.mark.parametrize("ab,ct", PAIRS)
+@pytest.mark.parametrize("layout", ["row/row/row", "col/row/row", "row/col/row", "col/col/col",
+                                    "row/row/col"])
+@pytest.mark.parametrize("sched", ["dp", "sk"])
+def test_dtypes_layouts_integer_exact(ab, ct, layout, sched, ws):
+    ao, bo, co = layout.split("/")
+    m, n, k = RAGGED
+    for blk in (SMALL_TILE[ab], BIG_TILE[ab]):
+        cfg = S.make_config(sched=sched, blk=blk, grid=0 if sched == "dp" else 7)
+        check_case(m, n, k, ab, ct, dist="int4", a_order=ao, b_order=bo, c_order=co, cfg=cfg, ws=ws)
+
+
+@pytest.mark.parametrize("ab,ct", PAIRS)
+def test_dtypes_real_valued_bound(ab, ct, ws):
+    m, n, k = RAGGED
+    dist = "uniform" if ab in ("f64", "f16") else "normal"
+    for sched in ("dp", "sk", "auto"):
+        cfg = S.make_config(sched=sched, blk=SMALL_TILE[ab])
+        check_case(m, n, k, ab, ct, dist=dist, cfg=cfg, ws=ws, seed=5)
+
+
+@pytest.mark.parametrize("ab,ct", [("f64", "f64"), ("bf16", "f32"), ("f16", "f16"), ("f8e4m3", "bf16")])
+def test_alpha_beta_integer_exact(ab, ct, ws):
+    m, n, k = 144, 272, 256
+    for c_order in ("row", "col"):
+        cfg = S.make_config(sched="sk", blk=SMALL_TILE[ab], grid=5)
+        check_case(m, n, k, ab, ct, dist="int4", alpha=2.0, beta=-1.0, c_order=c_order, cfg=cfg,
+                   ws=ws)
+
+
+@pytest.mark.parametrize("sched", ["2tsk", "dp1sk", "auto"])
+@pytest.mark.parametrize("slots", [4, 8, 13])
+def test_hybrids_on_few_slots(sched, slots, ws):
+    # wg_slots below the machine's capacity exercises full DP waves plus a
+    # Stream-K region on a small problem (t = 5 x 7 = 35 tiles of 64 x 64)
+    m, n, k = 320, 448, 320
+    cfg = S.make_config(sched=sched, blk=(64, 64, 16), wg_slots=slots)
+    check_case(m, n, k, "f64", "f64", dist="int4", cfg=cfg, ws=ws)
+    cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots)
+    check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
+
+
+def test_xcd_remap_off_same_bits(ws):
+    m, n, k = 512, 512, 2048
+    A, B = operands(m, n, k, "bf16", 3, "normal")
+    outs = []
+    for flags in (0, S.SK_FLAG_NO_XCD_REMAP):
+        cfg = S.make_config(sched="sk", blk=(128, 128, 64), grid=64, flags=flags)
+        Ct, _, _ = run_gemm(m, n, k, dev(A), dev(B), c_type="f32", cfg=cfg, ws=ws)
+        outs.append(Ct.view(torch.int32).cpu())
+    # same logical schedule and order: identical results
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_k_zero_and_alpha_zero_scale_c(ws):
+    m, n = 100, 64
+    rng = np.random.default_rng(1)
+    C0 = W.small_integers((m, n), rng)
+    for k, alpha in ((0, 1.0), (64, 0.0)):
+        A, B = operands(m, n, max(k, 1) if k else 16, "bf16", 1, "int4")
+        Ct, _, _ = run_gemm(m, n, k, dev(A), dev(B), c_type="f32", C0=C0, alpha=alpha, beta=-2.0, ws=ws)
+        assert np.array_equal(c_values(Ct, m, n, "row"), -2.0 * C0)
+        Ct, _, _ = run_gemm(m, n, k, dev(A), dev(B), c_type="bf16", C0=C0, alpha=alpha, beta=0.0, ws=ws)
+        assert np.array_equal(c_values(Ct, m, n, "row"), np.zeros((m, n)))
+
+
+def test_single_tile_deep_k_strong_scaling(ws):
+    # one output tile, k split over many workgroups (section 4; Fig. 8 shape family)
+    m, n, k = 128, 128, 16384
+    for ab, ct in (("bf16", "f32"), ("f64", "f64")):
+        cfg = S.make_config(sched="sk", blk=SMALL_TILE[ab] if ab == "f64" else (128, 128, 64), grid=8)
+        check_case(m, n, k, ab, ct, dist="int4", cfg=cfg, ws=ws)
+        cfg = S.make_config(sched="sk", blk=(64, 64, 16) if ab == "f64" else (128, 128, 64), grid=0)
+        check_case(m, n, k, ab, ct, dist="normal", cfg=cfg, ws=ws, seed=2)
+
+
+def test_workspace_flags_left_clean(ws):
+    # after many calls the flag region must be zero again (self-resetting)
+    m, n, k = CFG1
+    cfg = S.make_config(sched="sk", blk=(128, 128, 16), grid=200)
+    check_case(m, n, k, "f64", "f64", dist="int4", cfg=cfg, ws=ws, trace=False)
+    torch.cuda.synchronize()
+    st, plan = S.sk_plan(S.make_desc(m, n, k, 16, 16, 16, ab_type="f64", c_type="f64"), cfg)
+    flags = ws.buf[256:256 + plan.grid * 64].view(torch.int32).cpu()
+    assert int(flags.abs().sum()) == 0
