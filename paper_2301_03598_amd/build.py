@@ -32,8 +32,21 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src: str) -> str:
+def _headers():
+    return glob.glob(os.path.join(CSRC, "*.h*")) + [os.path.join(INCLUDE, "streamk.h")]
+
+
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [src, *_headers()])
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = ["hipcc", *CXXFLAGS, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -41,13 +54,15 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 0, verbose: bool = True) -> str:
+def build(jobs: int = 0, verbose: bool = True, force: bool = True) -> str:
+    """Compile every unit (``force=False``: only those older than their
+    sources or headers) and link the library."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4)
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,4 +75,5 @@ def build(jobs: int = 0, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build(int(sys.argv[1]) if len(sys.argv) > 1 else 0)
+    args = [a for a in sys.argv[1:] if not a.startswith("-")]
+    build(int(args[0]) if args else 0, force="--incremental" not in sys.argv)

@@ -35,6 +35,13 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
+// Bit casts go through by-value helpers: applied directly to an element of
+// an ext_vector_type lvalue, __builtin_bit_cast reads element 0 of the vector.
+__device__ __forceinline__ uint32_t f2u(float f) { return __builtin_bit_cast(uint32_t, f); }
+__device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ uint64_t d2u(double d) { return __builtin_bit_cast(uint64_t, d); }
+__device__ __forceinline__ double u2d(uint64_t u) { return __builtin_bit_cast(double, u); }
+
 enum class Dt { F64, F16, BF16, F8 };
 
 template <Dt D> struct DtTraits;
@@ -247,8 +254,8 @@ __device__ __forceinline__ void mma_ktile(typename C::Frag (&acc)[C::FM][C::FN],
             for (int i = 0; i < C::FM; ++i)
 #pragma unroll
                 for (int j = 0; j < C::FN; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[j], a0[i], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[j], a1[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], b1[j], acc[i][j], 0, 0, 0);
                 }
         }
     } else {
@@ -351,10 +358,13 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
 // ---------------------------------------------------------------------------
 // accumulator <-> (row, col) and the epilogue
 // ---------------------------------------------------------------------------
-// Output layout of a fragment.  The MFMAs compute D = B_frag * A_frag, i.e.
-// the transposed block, so lane l holds C row (l % MT) of the block and, in
-// accumulator register 4g+e, column 8g + 4(l / MT) + e (32x32 blocks) or
-// 4(l / 16) + e (16x16 f64 blocks): four consecutive columns per group g.
+// Output layout of a fragment.
+// 32x32 blocks (f16/bf16/f8): the MFMAs compute D = B_frag * A_frag, the
+// transposed block, so lane l holds C row (l % 32) of the block and, in
+// accumulator register 4g+e, column 8g + 4(l / 32) + e: four consecutive
+// columns per group g, stored as one vector.
+// 16x16 f64 blocks: D = A_frag * B_frag; lane l holds column (l % 16) and,
+// in register r, row 4r + (l / 16).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     uint32_t u = __builtin_bit_cast(uint32_t, f);
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
@@ -395,7 +405,7 @@ __device__ __forceinline__ void put4(char *p, const Acc (&v)[4], Acc beta, bool 
             for (int e = 0; e < 4; ++e) w[e] = v[e] + beta * (Acc)o[e];
         } else if constexpr (CT == SK_F32) {
             const u32x4 o = *(const u32x4 *)p;
-            for (int e = 0; e < 4; ++e) w[e] = v[e] + beta * (Acc)__builtin_bit_cast(float, o[e]);
+            for (int e = 0; e < 4; ++e) w[e] = v[e] + beta * (Acc)u2f(o[e]);
         } else {
             const u32x2 o = *(const u32x2 *)p;
             for (int e = 0; e < 4; ++e) {
@@ -410,8 +420,7 @@ __device__ __forceinline__ void put4(char *p, const Acc (&v)[4], Acc beta, bool 
     if constexpr (CT == SK_F64) {
         *(f64x4 *)p = f64x4{(double)w[0], (double)w[1], (double)w[2], (double)w[3]};
     } else if constexpr (CT == SK_F32) {
-        *(u32x4 *)p = u32x4{__builtin_bit_cast(uint32_t, (float)w[0]), __builtin_bit_cast(uint32_t, (float)w[1]),
-                            __builtin_bit_cast(uint32_t, (float)w[2]), __builtin_bit_cast(uint32_t, (float)w[3])};
+        *(u32x4 *)p = u32x4{f2u((float)w[0]), f2u((float)w[1]), f2u((float)w[2]), f2u((float)w[3])};
     } else {
         uint32_t h[4];
         for (int e = 0; e < 4; ++e)
@@ -436,7 +445,32 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
     const int coll = tn * C::BN + wn * C::WTN + 4 * (lane / C::MT);
     const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
     const bool rd = P.beta != 0.0;
-    const bool fast = P.c_vec && (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
+    const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
+    const bool fast = P.c_vec && interior;
+    if constexpr (C::MT == 16) {
+        // f64: one element per store; a lane group of 16 writes 128
+        // consecutive bytes of one row
+        const int r0 = tm * C::BM + wm * C::WTM + (lane >> 4);
+        const int c0 = tn * C::BN + wn * C::WTN + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) {
+#pragma unroll
+            for (int j = 0; j < C::FN; ++j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = r0 + i * 16 + 4 * r, col = c0 + j * 16;
+                    if (interior || (row < P.m && col < P.n)) {
+                        char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+                        Acc w = alpha * acc[i][j][r];
+                        if (rd) w = w + beta * load_c<CT, Acc>(q);
+                        put_c<CT, Acc>(q, w);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < C::FM; ++i) {
         const int row = rowl + i * C::MT;
@@ -497,13 +531,13 @@ __device__ __forceinline__ void store_partial(char *slot, typename C::Frag (&acc
                 const int v = (i * C::FN + j) * CPF + s;
                 u32x4 w;
                 if constexpr (PER == 4) {
-                    w[0] = __builtin_bit_cast(uint32_t, acc[i][j][4 * s + 0]);
-                    w[1] = __builtin_bit_cast(uint32_t, acc[i][j][4 * s + 1]);
-                    w[2] = __builtin_bit_cast(uint32_t, acc[i][j][4 * s + 2]);
-                    w[3] = __builtin_bit_cast(uint32_t, acc[i][j][4 * s + 3]);
+                    w[0] = f2u(acc[i][j][4 * s + 0]);
+                    w[1] = f2u(acc[i][j][4 * s + 1]);
+                    w[2] = f2u(acc[i][j][4 * s + 2]);
+                    w[3] = f2u(acc[i][j][4 * s + 3]);
                 } else {
-                    uint64_t x0 = __builtin_bit_cast(uint64_t, acc[i][j][2 * s + 0]);
-                    uint64_t x1 = __builtin_bit_cast(uint64_t, acc[i][j][2 * s + 1]);
+                    const uint64_t x0 = d2u(acc[i][j][2 * s + 0]);
+                    const uint64_t x1 = d2u(acc[i][j][2 * s + 1]);
                     w[0] = (uint32_t)x0; w[1] = (uint32_t)(x0 >> 32);
                     w[2] = (uint32_t)x1; w[3] = (uint32_t)(x1 >> 32);
                 }
@@ -525,13 +559,13 @@ __device__ __forceinline__ void add_partial(const char *slot, typename C::Frag (
                 const int v = (i * C::FN + j) * CPF + s;
                 const u32x4 w = *(const u32x4 *)(slot + ((int64_t)v * THREADS + tid) * 16);
                 if constexpr (PER == 4) {
-                    acc[i][j][4 * s + 0] += __builtin_bit_cast(float, w[0]);
-                    acc[i][j][4 * s + 1] += __builtin_bit_cast(float, w[1]);
-                    acc[i][j][4 * s + 2] += __builtin_bit_cast(float, w[2]);
-                    acc[i][j][4 * s + 3] += __builtin_bit_cast(float, w[3]);
+                    acc[i][j][4 * s + 0] += u2f(w[0]);
+                    acc[i][j][4 * s + 1] += u2f(w[1]);
+                    acc[i][j][4 * s + 2] += u2f(w[2]);
+                    acc[i][j][4 * s + 3] += u2f(w[3]);
                 } else {
-                    acc[i][j][2 * s + 0] += __builtin_bit_cast(double, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
-                    acc[i][j][2 * s + 1] += __builtin_bit_cast(double, (uint64_t)w[2] | ((uint64_t)w[3] << 32));
+                    acc[i][j][2 * s + 0] += u2d((uint64_t)w[0] | ((uint64_t)w[1] << 32));
+                    acc[i][j][2 * s + 1] += u2d((uint64_t)w[2] | ((uint64_t)w[3] << 32));
                 }
                 if (s == CPF - 1) __builtin_amdgcn_sched_barrier(0);
             }
