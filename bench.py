@@ -1,0 +1,350 @@
+#!/usr/bin/env python3
+"""Stream-K GEMM benchmark on one MI355X.
+
+Workload (one "step"): the geometry sweep -- 2048 GEMMs with m, n, k drawn
+log-uniformly from [128, 8192] (seed 1, rounded to multiples of 8), FP16
+inputs uniform in [-1, 1], FP32 accumulation and output, alpha = 1,
+beta = 0, row-major -- each run once through sk_gemm with the library's
+default schedule (two-tile Stream-K + data-parallel hybrid, one tile per
+precision).  Inputs are resident in HBM before timing starts.
+
+Reported on one JSON line: aggregate TFLOP/s of the step (value), % of the
+FP16 dense MFMA peak, per-GEMM latency p50/p99, the same sweep under the
+data-parallel and basic Stream-K schedules (the paper's comparison), the
+roofline of the dominant kernel measured with HIP events on the launch
+stream, and the CPU oracle timed on a bounded sample of the same workload.
+
+`--extended` adds the FP64 sweep and the precision set (BF16 and FP8 on
+8192^3, 256x256x65536, 4096x1024x4096).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f16": 2516.6, "bf16": 2516.6, "f8e4m3": 5033.2}
+HBM_GBS = 8000.0
+METRIC = "TFLOP/s and % dtype MFMA peak, Stream-K vs data-parallel tiling; p50/p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+class Sweep:
+    """All problems of a sweep with operands resident in rotating device
+    arenas (consecutive problems never share operand memory)."""
+
+    def __init__(self, shapes, ab, ct, seed, arena_bytes=4 << 30):
+        import torch
+        import workloads as W
+        from paper_2301_03598_amd import streamk as S
+        self.shapes = shapes
+        self.ab, self.ct = ab, ct
+        eb = W.DTYPE_BYTES[ab]
+        cb = W.DTYPE_BYTES[ct]
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        tdt, cdt = W.torch_dtype(ab), W.torch_dtype(ct)
+
+        def arena(nbytes, dt, esize, fill):
+            t = torch.empty(nbytes // esize, dtype=dt, device="cuda")
+            if fill:
+                t.uniform_(-1.0, 1.0, generator=gen)
+            return t
+        self.A = arena(arena_bytes, tdt, eb, True)
+        self.B = arena(arena_bytes, tdt, eb, True)
+        self.C = arena(arena_bytes, cdt, cb, False)
+        offs = {"A": 0, "B": 0, "C": 0}
+
+        def place(name, nelem, esize, total):
+            nbytes = (nelem * esize + 255) // 256 * 256
+            if offs[name] + nbytes > total:
+                offs[name] = 0
+            o = offs[name]
+            offs[name] += nbytes
+            return o
+        self.descs = (S.sk_gemm_desc_t * len(shapes))()
+        self.flops = []
+        for i, (m, n, k) in enumerate(shapes):
+            oa = place("A", m * k, eb, arena_bytes)
+            ob = place("B", k * n, eb, arena_bytes)
+            oc = place("C", m * n, cb, arena_bytes)
+            self.descs[i] = S.make_desc(m, n, k, self.A.data_ptr() + oa, self.B.data_ptr() + ob,
+                                        self.C.data_ptr() + oc, ab_type=ab, c_type=ct)
+            self.flops.append(2.0 * m * n * k)
+        self.total_flops = sum(self.flops)
+
+
+class Runner:
+    """Launches sk_gemm for every problem of a sweep on the current stream,
+    with a timing event pair around every launch."""
+
+    def __init__(self, sweep, cfg):
+        import torch
+        from paper_2301_03598_amd import runtime as R
+        from paper_2301_03598_amd import streamk as S
+        self.S = S
+        self.sweep = sweep
+        self.cfg = cfg
+        self.L = S.lib()
+        need = 256
+        self.plans = []
+        for i in range(len(sweep.shapes)):
+            st, pl = S.sk_plan(sweep.descs[i], cfg)
+            S.check(st, "sk_plan")
+            self.plans.append(pl)
+            need = max(need, pl.workspace_bytes)
+        self.ws = R.Workspace("cuda", need)
+        self.stream = torch.cuda.current_stream()
+        self.sptr = ctypes.c_void_p(self.stream.cuda_stream)
+        self.wsp = ctypes.c_void_p(self.ws.ptr)
+        self.cfgp = ctypes.byref(cfg) if cfg is not None else None
+        self.dptrs = [ctypes.byref(sweep.descs[i]) for i in range(len(sweep.shapes))]
+        n = len(sweep.shapes)
+        self.ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        self.ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+    def step(self, durations=None):
+        L, ws, nb = self.L, self.wsp, self.ws.nbytes
+        for i, d in enumerate(self.dptrs):
+            self.ev0[i].record(self.stream)
+            st = L.sk_gemm(d, self.cfgp, ws, nb, self.sptr)
+            self.ev1[i].record(self.stream)
+            if st != 0:
+                raise RuntimeError(f"sk_gemm failed on problem {i}: {self.S.sk_status_string(st)}")
+        if durations is not None:
+            self.stream.synchronize()
+            durations.append([self.ev0[i].elapsed_time(self.ev1[i]) for i in range(len(self.dptrs))])
+
+
+def geomean(xs):
+    xs = [x for x in xs if x > 0]
+    return math.exp(sum(math.log(x) for x in xs) / len(xs)) if xs else 0.0
+
+
+def pct(xs, q):
+    ys = sorted(xs)
+    if not ys:
+        return 0.0
+    idx = min(len(ys) - 1, max(0, int(math.ceil(q / 100.0 * len(ys))) - 1))
+    return ys[idx]
+
+
+def schedule_leg(sweep, sched, passes=2):
+    """Aggregate and geomean TFLOP/s of a sweep under one schedule."""
+    import torch
+    from paper_2301_03598_amd import streamk as S
+    run = Runner(sweep, S.make_config(sched=sched))
+    warm = []
+    run.step(warm)                  # warm-up pass
+    durs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        run.step(durs)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / passes
+    per = [sum(d[i] for d in durs) / len(durs) for i in range(len(sweep.shapes))]
+    tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
+    return {"tflops": round(sweep.total_flops / wall / 1e12, 2),
+            "kernel_tflops": round(sweep.total_flops / (sum(per) * 1e-3) / 1e12, 2),
+            "geomean_tflops": round(geomean(tf), 2),
+            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, warm + durs
+
+
+def cpu_baseline(budget_flops=1.2e11):
+    """The CPU oracle, as it stands, on a bounded sample of the sweep: the
+    problems in draw order whose flops fit the budget, FP16 inputs."""
+    import oracle
+    import workloads as W
+    shapes = W.sweep_shapes()
+    pick, tot = [], 0.0
+    for (m, n, k) in shapes:
+        f = 2.0 * m * n * k
+        if tot + f <= budget_flops:
+            pick.append((m, n, k))
+            tot += f
+    oracle.build(force=False)
+    t = 0.0
+    for i, (m, n, k) in enumerate(pick):
+        A, B = W.gemm_operands(m, n, k, "f16", 1000 + i, "uniform")
+        t0 = time.perf_counter()
+        oracle.gemm(m, n, k, A, B, c_type="f32")
+        t += time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0) or len(os.sched_getaffinity(0)))
+    return {"value": round(tot / t / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(pick)} sweep problems (draw order, FP16->FP32) fitting a "
+                      f"{budget_flops:.1e}-flop budget; {tot:.3e} flop in {t:.1f} s"}
+
+
+def extended():
+    """FP64 sweep under the three schedules and the precision set."""
+    import torch
+    import workloads as W
+    from paper_2301_03598_amd import runtime as R
+    from paper_2301_03598_amd import streamk as S
+    out = {}
+    sw = Sweep(W.sweep_shapes(), "f64", "f64", seed=11)
+    for sched in ("dp", "sk", "auto"):
+        out[f"f64_sweep_{sched}"], _, _ = schedule_leg(sw, sched, passes=1)
+        log("f64", sched, out[f"f64_sweep_{sched}"])
+    del sw
+    torch.cuda.empty_cache()
+    ws = R.Workspace("cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    for name, (m, n, k) in W.PRECISION_SHAPES.items():
+        for ab, ct in (("bf16", "bf16"), ("f8e4m3", "bf16")):
+            A = torch.empty(m * k, dtype=W.torch_dtype(ab), device="cuda")
+            B = torch.empty(k * n, dtype=W.torch_dtype(ab), device="cuda")
+            W.device_fill_(A, "normal", gen)
+            W.device_fill_(B, "normal", gen)
+            C = torch.empty(m * n, dtype=W.torch_dtype(ct), device="cuda")
+            for sched in ("dp", "auto"):
+                cfg = S.make_config(sched=sched)
+                d = S.make_desc(m, n, k, A, B, C, ab_type=ab, c_type=ct,
+                                a_scale=1.0, b_scale=1.0)
+                st, pl = S.sk_plan(d, cfg)
+                S.check(st, "sk_plan")
+                ws.ensure(pl.workspace_bytes)
+                s = torch.cuda.current_stream().cuda_stream
+                for _ in range(3):
+                    S.check(S.sk_gemm(d, cfg, ws.ptr, ws.nbytes, s), "sk_gemm")
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 10
+                e0.record()
+                for _ in range(reps):
+                    S.sk_gemm(d, cfg, ws.ptr, ws.nbytes, s)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+                key = f"{name}_{m}x{n}x{k}_{ab}_{sched}"
+                out[key] = {"ms": round(ms, 4), "tflops": round(tf, 1),
+                            "pct_peak": round(100 * tf / PEAK_TFLOPS[ab], 2),
+                            "sched": S.SCHED_NAME.get(pl.sched, pl.sched), "grid": pl.grid}
+                log(key, out[key])
+            del A, B, C
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--extended", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the Stream-K path shards by problem or by C slab, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2301_03598_amd import streamk as S
+    S.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    shapes = W.sweep_shapes()
+    log(f"sweep: {len(shapes)} problems; allocating operands")
+    sweep = Sweep(shapes, "f16", "f32", seed=1)
+    torch.cuda.synchronize()
+    run = Runner(sweep, S.make_config(sched="auto"))
+    kinds = {}
+    for pl in run.plans:
+        kinds[S.SCHED_NAME.get(pl.sched, str(pl.sched))] = kinds.get(S.SCHED_NAME.get(pl.sched, str(pl.sched)), 0) + 1
+    log("schedules resolved:", kinds)
+
+    all_durs = []
+    for w in range(args.warmup):
+        run.step(all_durs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed = []
+    for _ in range(args.steps):
+        run.step(timed)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    value = sweep.total_flops / (ms_step * 1e-3) / 1e12
+    log(f"hybrid sweep: {ms_step:.2f} ms/step, {value:.1f} TFLOP/s")
+    all_durs += timed
+    per = [sum(d[i] for d in timed) / len(timed) for i in range(len(shapes))]
+    lat_us = [x * 1e3 for x in per]
+    tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
+
+    compare = {}
+    sk_launch_durs, sk_launch_flops = [], []
+    # every launch of the Stream-K kernel in this run is timed; the roofline
+    # averages over exactly the launches a kernel-trace profile sees
+    for d in all_durs:
+        sk_launch_durs += d
+        sk_launch_flops += sweep.flops
+    if not args.no_compare:
+        dp, tf_dp, _ = schedule_leg(sweep, "dp")
+        sk, tf_sk, sk_durs = schedule_leg(sweep, "sk")
+        for d in sk_durs:               # same kernel symbol as the hybrid
+            sk_launch_durs += d
+            sk_launch_flops += sweep.flops
+        compare = {"dp": dp, "sk_basic": sk,
+                   "hybrid": {"tflops": round(value, 2), "geomean_tflops": round(geomean(tf), 2),
+                              "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2)},
+                   "geomean_speedup_hybrid_vs_dp": round(geomean([a / b for a, b in zip(tf, tf_dp)]), 3),
+                   "geomean_speedup_sk_vs_dp": round(geomean([a / b for a, b in zip(tf_sk, tf_dp)]), 3),
+                   "min_speedup_hybrid_vs_dp": round(min(a / b for a, b in zip(tf, tf_dp)), 3),
+                   "max_speedup_hybrid_vs_dp": round(max(a / b for a, b in zip(tf, tf_dp)), 3)}
+        log("compare:", compare)
+    avg_ms = sum(sk_launch_durs) / len(sk_launch_durs)
+    avg_flops = sum(sk_launch_flops) / len(sk_launch_flops)
+    achieved = avg_flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4), "traffic": None,
+                "kernel": "sk_kernel<F16, 256x256x64, A k-contiguous, B n-contiguous>",
+                "launches": len(sk_launch_durs), "avg_launch_us": round(avg_ms * 1e3, 3),
+                "avg_flops_per_launch": avg_flops}
+
+    ext = extended() if args.extended else None
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    if cpu:
+        log("cpu baseline:", cpu)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": "geometry sweep: 2048 GEMMs, m,n,k log-uniform in [128,8192] rounded "
+                               "to multiples of 8 (seed 1); FP16 inputs U[-1,1], FP32 accumulate "
+                               "and output; alpha=1, beta=0; row-major; library default schedule "
+                               "(two-tile Stream-K + DP hybrid)",
+                   "problems": len(shapes), "flops_per_step": sweep.total_flops,
+                   "tile": f"{run.plans[0].blk_m}x{run.plans[0].blk_n}x{run.plans[0].blk_k}",
+                   "schedules": kinds},
+        "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2),
+        "latency_us": {"p50": round(pct(lat_us, 50), 2), "p99": round(pct(lat_us, 99), 2)},
+        "geomean_tflops": round(geomean(tf), 2),
+        "compare": compare,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if ext is not None:
+        line["extended"] = ext
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
