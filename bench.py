@@ -237,6 +237,98 @@ def extended():
     return out
 
 
+def grouped_leg(tune: bool = True):
+    """512 BF16 GEMMs (seed 3): one grouped persistent launch captured in a
+    HIP graph and replayed, against 512 separate sk_gemm launches; the
+    grouped configuration comes from the autotuner (library default shown
+    beside it)."""
+    import torch
+    import workloads as W
+    from paper_2301_03598_amd import runtime as R
+    from paper_2301_03598_amd import streamk as S
+    from paper_2301_03598_amd import tune as T
+    shapes = W.grouped_shapes()
+    sw = Sweep(shapes, "bf16", "f32", seed=3, arena_bytes=6 << 30)
+    descs = list(sw.descs)
+    flops = sw.total_flops
+    out = {"problems": len(shapes), "flops": flops}
+    # separate launches, library default per problem
+    run = Runner(sw, S.make_config(sched="auto"))
+    run.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        run.step()
+    torch.cuda.synchronize()
+    sep_ms = (time.perf_counter() - t0) / 3 * 1e3
+    out["separate_launches"] = {"ms": round(sep_ms, 3), "tflops": round(flops / sep_ms / 1e9, 1)}
+
+    def grouped_time(cfg, label):
+        ws = R.Workspace("cuda")
+        arr = (S.sk_gemm_desc_t * len(descs))(*descs)
+        st, plan = S.sk_plan(arr, cfg)
+        S.check(st, "sk_plan")
+        ws.ensure(plan.workspace_bytes)
+        R.gemm_grouped(descs, cfg=cfg, ws=ws)
+        torch.cuda.synchronize()
+        stream = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            _, keep = R.gemm_grouped(descs, cfg=cfg, ws=ws, stream=stream)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del keep
+        return {"ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 1),
+                "sched": S.SCHED_NAME.get(plan.sched, plan.sched), "grid": plan.grid,
+                "tile": f"{plan.blk_m}x{plan.blk_n}x{plan.blk_k}", "label": label}
+    out["grouped_default"] = grouped_time(S.make_config(sched="auto"), "library default")
+    if tune:
+        tuner = T.Tuner()
+        best = tuner.tune_grouped(descs, "bf16", "grouped512", reps=2)
+        out["grouped_tuned"] = grouped_time(best.config(), "autotuned")
+    best_g = max(v["tflops"] for k, v in out.items() if k.startswith("grouped_"))
+    out["speedup_grouped_vs_separate"] = round(best_g / out["separate_launches"]["tflops"], 3)
+    del sw
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_leg(duration_s: float = 1.0, rate: float = 20000.0):
+    """Poisson arrivals of mixed BF16/FP16 GEMMs (seed 4) through the
+    continuous-batching server: p50/p99 latency and sustained TFLOP/s."""
+    import torch
+    import workloads as W
+    from paper_2301_03598_amd import serve as SV
+    trace = W.serving_trace(rate_per_s=rate, duration_s=duration_s, seed=4)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    pools = {}
+    for dt in ("bf16", "f16"):
+        t = torch.empty(1 << 28, dtype=W.torch_dtype(dt), device="cuda")
+        t.normal_(0.0, 1.0, generator=gen)
+        pools[dt] = t
+    reqs = SV.make_requests(trace, pools, seed=4)
+    srv = SV.Server(pools, hbm_budget=64 << 30, out_bytes=24 << 30, streams=2, max_batch=512)
+    st = srv.run(reqs)
+    offered = sum(r.flops for r in reqs) / duration_s / 1e12
+    res = {"requests": st.requests, "completed": st.completed, "duration_s": duration_s,
+           "offered_tflops": round(offered, 1), "sustained_tflops": round(st.sustained_tflops, 1),
+           "makespan_s": round(st.makespan_s, 3), "p50_ms": round(st.p50_ms, 3),
+           "p99_ms": round(st.p99_ms, 3), "launches": st.launches,
+           "mean_batch": round(st.mean_batch, 1), "max_queue": st.max_queue}
+    del pools, srv
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +409,15 @@ def main():
                 "launches": len(sk_launch_durs), "avg_launch_us": round(avg_ms * 1e3, 3),
                 "avg_flops_per_launch": avg_flops}
 
-    ext = extended() if args.extended else None
+    ext = None
+    if args.extended:
+        del sweep, run
+        torch.cuda.empty_cache()
+        ext = extended()
+        ext["grouped"] = grouped_leg()
+        log("grouped:", ext["grouped"])
+        ext["serving"] = serving_leg()
+        log("serving:", ext["serving"])
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     if cpu:
         log("cpu baseline:", cpu)

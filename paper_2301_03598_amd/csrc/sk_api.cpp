@@ -69,6 +69,9 @@ bool supported_pair(int ab, int c) {
 
 bool is_order(int o) { return o == SK_ROW_MAJOR || o == SK_COL_MAJOR; }
 
+// Largest leading dimension of A or B, in bytes (4 MiB: 2M FP16 elements).
+constexpr int64_t kMaxRowBytes = 1LL << 22;
+
 sk_status_t validate(const sk_gemm_desc_t &d) {
     if (d.m < 0 || d.n < 0 || d.k < 0) return SK_ERR_INVALID_VALUE;
     if (d.m > (1LL << 30) || d.n > (1LL << 30) || d.k > (1LL << 30)) return SK_ERR_INVALID_VALUE;
@@ -99,6 +102,9 @@ sk_status_t validate(const sk_gemm_desc_t &d) {
     const int64_t lda = d.lda ? d.lda : a_ext, ldb = d.ldb ? d.ldb : b_ext;
     if (((uintptr_t)d.A & 15u) || ((uintptr_t)d.B & 15u)) return SK_ERR_MISALIGNED;
     if (lda % vec || ldb % vec || a_ext % vec || b_ext % vec) return SK_ERR_MISALIGNED;
+    // the kernels address one k-tile of an operand with 32-bit offsets
+    const int64_t eb = dtype_bytes(d.ab_type);
+    if (lda * eb > kMaxRowBytes || ldb * eb > kMaxRowBytes) return SK_ERR_INVALID_VALUE;
     return SK_OK;
 }
 
@@ -321,7 +327,11 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The descriptor-table region is always reserved (a few hundred bytes per
+// problem), so one size serves sk_gemm and sk_gemm_grouped alike, including
+// a grouped call with a single problem.
 Layout layout_for(const sk_plan_t &pl, int ab, int32_t count, bool grouped) {
+    grouped = true;
     Layout L;
     size_t off = WS_HEADER;
     if (pl.sched != SK_SCHED_DP && pl.grid > 0) {

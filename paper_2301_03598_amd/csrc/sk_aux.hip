@@ -1,41 +1,10 @@
-// Auxiliary kernels (C = beta*C for k == 0 / alpha == 0, grouped-table
-// preparation) and the lookup over the per-(dtype, tile) instance units.
+// Auxiliary kernels: C = beta*C for k == 0 / alpha == 0, and the grouped
+// problem-table preparation.
 #include <hip/hip_runtime.h>
 
 #include "sk_internal.h"
 
 namespace sk {
-
-KernelEntry pick_f64_128(const KernelKey &k);
-KernelEntry pick_f64_64(const KernelKey &k);
-KernelEntry pick_f16_256(const KernelKey &k);
-KernelEntry pick_f16_128(const KernelKey &k);
-KernelEntry pick_bf16_256(const KernelKey &k);
-KernelEntry pick_bf16_128(const KernelKey &k);
-KernelEntry pick_f8_256(const KernelKey &k);
-KernelEntry pick_f8_128(const KernelKey &k);
-
-KernelEntry find_kernel(const KernelKey &k) {
-    switch (k.ab_type) {
-    case SK_F64:
-        if (k.bm == 128 && k.bn == 128) return pick_f64_128(k);
-        if (k.bm == 64 && k.bn == 64) return pick_f64_64(k);
-        break;
-    case SK_F16:
-        if (k.bm == 256 && k.bn == 256) return pick_f16_256(k);
-        if (k.bm == 128 && k.bn == 128) return pick_f16_128(k);
-        break;
-    case SK_BF16:
-        if (k.bm == 256 && k.bn == 256) return pick_bf16_256(k);
-        if (k.bm == 128 && k.bn == 128) return pick_bf16_128(k);
-        break;
-    case SK_F8_E4M3:
-        if (k.bm == 256 && k.bn == 256) return pick_f8_256(k);
-        if (k.bm == 128 && k.bn == 128) return pick_f8_128(k);
-        break;
-    }
-    return KernelEntry{nullptr, nullptr};
-}
 
 // ---------------------------------------------------------------------------
 // C = beta * C over an m x n row-major view (the caller has already folded a

@@ -23,15 +23,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "sk_internal.h"
 
 namespace sk {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -41,6 +47,18 @@ __device__ __forceinline__ uint32_t f2u(float f) { return __builtin_bit_cast(uin
 __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
 __device__ __forceinline__ uint64_t d2u(double d) { return __builtin_bit_cast(uint64_t, d); }
 __device__ __forceinline__ double u2d(uint64_t u) { return __builtin_bit_cast(double, u); }
+
+// Compile-time loop: f(integral_constant<int, 0>), ..., f(<N-1>).  Used
+// where accumulator fragments are indexed, so every index is a constant even
+// when the body is too large for the loop unroller.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 enum class Dt { F64, F16, BF16, F8 };
 
@@ -92,8 +110,13 @@ struct Cfg {
 };
 
 // LDS byte offset of 16-byte chunk c of row r (128-byte rows, XOR swizzle).
+// The LDS serves a 16-byte-per-lane access 16 lanes per cycle across 64
+// banks (256 bytes): two consecutive 128-byte rows share one bank row, so
+// the swizzle key is row/2.  Then 16 lanes reading the same chunk of 16
+// consecutive rows, and 16 lanes writing 8 chunks of each of 2 consecutive
+// rows, all hit distinct banks.
 __device__ __forceinline__ uint32_t lds_off(uint32_t row, uint32_t chunk) {
-    return row * 128u + (((chunk ^ row) & 7u) << 4);
+    return row * 128u + (((chunk ^ (row >> 1)) & 7u) << 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -112,32 +135,42 @@ struct Stage {
     static constexpr int KB = BK / L;               // k-blocks (threads) per mn block
     static constexpr int PIECE = L * E;             // bytes per mn-row piece
 
-    const char *base;      // thread's first load address at k-tile 0
-    int64_t kstep;         // bytes per k-tile
-    int64_t lstride;       // bytes between this thread's consecutive loads
+    // Load i of k-tile kt reads 16 bytes at ub + kt*ustep + i*ustride + voff
+    // through a buffer resource: the base, k-tile step and load stride are
+    // uniform (scalar registers), the lane offset is one 32-bit VGPR, and a
+    // lane whose data lie outside the matrix gets an offset past the
+    // resource's range, which the hardware returns as zeros.
+    const char *ub;
+    int64_t ustep;
+    uint32_t ustride;
+    uint32_t voff;
     int rows_valid;        // number of valid leading loads (row edge), KC only
     bool mn_valid;         // !KC: this thread's mn block lies inside the matrix
     int kofs;              // k offset (elements) of this thread's first load within a k-tile
     uint32_t lds0;         // LDS offset of the first store (KC) / row base (!KC)
     u32x4 r[NL];
 
+    static constexpr uint32_t OOB = 0x80000000u;
+
     __device__ __forceinline__ void init(const void *ptr, int64_t ld, int row0, int rows_total,
                                          int tid) {
         const char *p = (const char *)ptr;
         if constexpr (KC) {
-            int rr = tid >> 3, c = tid & 7;
-            base = p + ((int64_t)(row0 + rr) * ld + c * VEC) * E;
-            kstep = (int64_t)BK * E;
-            lstride = (int64_t)32 * ld * E;
-            int rem = rows_total - row0 - rr;           // rows left for this thread
+            const int rr = tid >> 3, c = tid & 7;
+            ub = p + (int64_t)row0 * ld * E;
+            ustep = (int64_t)BK * E;
+            ustride = (uint32_t)(32 * ld * E);
+            voff = (uint32_t)(((int64_t)rr * ld + c * VEC) * E);
+            const int rem = rows_total - row0 - rr;     // rows left for this thread
             rows_valid = rem <= 0 ? 0 : (rem + 31) / 32;
             kofs = c * VEC;
             lds0 = lds_off(rr, c);
         } else {
-            int kb = tid % KB, mb = tid / KB;
-            base = p + ((int64_t)(kb * L) * ld + row0 + mb * VEC) * E;
-            kstep = (int64_t)BK * ld * E;
-            lstride = (int64_t)ld * E;
+            const int kb = tid % KB, mb = tid / KB;
+            ub = p + (int64_t)row0 * E;
+            ustep = (int64_t)BK * ld * E;
+            ustride = (uint32_t)(ld * E);
+            voff = (uint32_t)(((int64_t)(kb * L) * ld + mb * VEC) * E);
             mn_valid = row0 + mb * VEC < rows_total;
             kofs = kb * L;
             lds0 = (uint32_t)(mb * VEC);                // first row of the block
@@ -146,30 +179,21 @@ struct Stage {
 
     // Issue the loads of k-tile kt.  Out-of-range data are zero.
     __device__ __forceinline__ void load(int kt, int K, bool interior) {
-        const char *p = base + kt * kstep;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
         if constexpr (KC) {
-            if (interior) {
+            const bool kv = interior || kt * BK + kofs < K;
 #pragma unroll
-                for (int i = 0; i < NL; ++i) r[i] = *(const u32x4 *)(p + i * lstride);
-            } else {
-                bool kv = kt * BK + kofs < K;
-#pragma unroll
-                for (int i = 0; i < NL; ++i) {
-                    if (kv && i < rows_valid) r[i] = *(const u32x4 *)(p + i * lstride);
-                    else r[i] = u32x4{0u, 0u, 0u, 0u};
-                }
+            for (int i = 0; i < NL; ++i) {
+                const uint32_t o = (interior || (kv && i < rows_valid)) ? voff : OOB;
+                r[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, i * ustride, 0));
             }
         } else {
-            if (interior) {
+            const int k0 = kt * BK + kofs;
 #pragma unroll
-                for (int j = 0; j < NL; ++j) r[j] = *(const u32x4 *)(p + j * lstride);
-            } else {
-                int k0 = kt * BK + kofs;
-#pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    if (mn_valid && k0 + j < K) r[j] = *(const u32x4 *)(p + j * lstride);
-                    else r[j] = u32x4{0u, 0u, 0u, 0u};
-                }
+            for (int j = 0; j < NL; ++j) {
+                const uint32_t o = (interior || (mn_valid && k0 + j < K)) ? voff : OOB;
+                r[j] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, j * ustride, 0));
             }
         }
     }
@@ -222,90 +246,85 @@ struct Stage {
 };
 
 // ---------------------------------------------------------------------------
-// MFMA on one k-tile held in LDS
+// MFMA operand fragments
+//
+// 32x32 MFMAs (f16/bf16/f8): lane l feeds row (l % 32) of the A block (and
+// column (l % 32) of the B block) with a contiguous run of k from lane group
+// q = l / 32: 8 values (one 16-byte chunk) for f16/bf16, 32 values (two
+// chunks) for f8.  A k-tile (8 chunks) is NSUB such k-steps.
+// 16x16x4 f64 MFMA: lane group q = l / 16 supplies one k value per MFMA; one
+// chunk read gives a lane two consecutive k values (2q and 2q+1 of an 8-k
+// half of the row) consumed by two MFMAs.  A and B use the same assignment,
+// so every k of the k-tile meets its partner exactly once.
 // ---------------------------------------------------------------------------
 template <class C>
-__device__ __forceinline__ void mma_ktile(typename C::Frag (&acc)[C::FM][C::FN], const char *ldsA,
-                                          const char *ldsB, int lane, int wm, int wn) {
-    if constexpr (C::DT == Dt::F64) {
-        // v_mfma_f64_16x16x4: lane group q = lane/16 supplies one k value per
-        // MFMA.  One 16-byte chunk read gives a lane two consecutive k values,
-        // consumed by two MFMAs (group q covers k = 2q, 2q+1 of each 8-k
-        // half of the chunk row); A and B use the same assignment.
-        const int r16 = lane & 15, q = lane >> 4;
-        const uint32_t arow = (uint32_t)(wm * C::WTM + r16), brow = (uint32_t)(wn * C::WTN + r16);
+struct Frag {
+    static constexpr int CPM = (C::DT == Dt::F8) ? 2 : 1;          // chunks per lane per operand
+    static constexpr int NSUB = (C::DT == Dt::F64) ? 2 : 8 / (2 * CPM);
+    u32x4 a[C::FM][CPM], b[C::FN][CPM];
+};
+
+template <class C>
+__device__ __forceinline__ int frag_chunk(int ks, int q, int s) {
+    if constexpr (C::DT == Dt::F64) return ks * 4 + q;
+    else return ks * 2 * Frag<C>::CPM + q * Frag<C>::CPM + s;
+}
+
+template <class C>
+__device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const char *ldsB, uint32_t arow,
+                                           uint32_t brow, int ks, int q) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = h * 4 + q;
-            double a0[C::FM], a1[C::FM], b0[C::FN], b1[C::FN];
+    for (int s = 0; s < Frag<C>::CPM; ++s) {
+        const int c = frag_chunk<C>(ks, q, s);
 #pragma unroll
-            for (int i = 0; i < C::FM; ++i) {
-                const double *pa = (const double *)(ldsA + lds_off(arow + i * 16, c));
-                a0[i] = pa[0];
-                a1[i] = pa[1];
-            }
+        for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
 #pragma unroll
-            for (int j = 0; j < C::FN; ++j) {
-                const double *pb = (const double *)(ldsB + lds_off(brow + j * 16, c));
-                b0[j] = pb[0];
-                b1[j] = pb[1];
-            }
-#pragma unroll
-            for (int i = 0; i < C::FM; ++i)
-#pragma unroll
-                for (int j = 0; j < C::FN; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], b1[j], acc[i][j], 0, 0, 0);
-                }
-        }
-    } else {
-        // 32x32 MFMAs: lane group q = lane/32 supplies a contiguous run of k
-        // (8 for f16/bf16: one chunk; 32 for f8: two chunks).
-        constexpr int CPM = (C::DT == Dt::F8) ? 2 : 1;    // chunks per lane per MFMA
-        constexpr int NSUB = 8 / (2 * CPM);                // MFMAs along k per k-tile
-        const int r32 = lane & 31, q = lane >> 5;
-        const uint32_t arow = (uint32_t)(wm * C::WTM + r32), brow = (uint32_t)(wn * C::WTN + r32);
-#pragma unroll
-        for (int ks = 0; ks < NSUB; ++ks) {
-            u32x4 a[C::FM][CPM], b[C::FN][CPM];
-#pragma unroll
-            for (int s = 0; s < CPM; ++s) {
-                const int c = ks * 2 * CPM + q * CPM + s;
-#pragma unroll
-                for (int i = 0; i < C::FM; ++i) a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * 32, c));
-#pragma unroll
-                for (int j = 0; j < C::FN; ++j) b[j][s] = *(const u32x4 *)(ldsB + lds_off(brow + j * 32, c));
-            }
-#pragma unroll
-            for (int i = 0; i < C::FM; ++i)
-#pragma unroll
-                for (int j = 0; j < C::FN; ++j) {
-                    if constexpr (C::DT == Dt::BF16) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, b[j][0]), __builtin_bit_cast(bf16x8, a[i][0]),
-                            acc[i][j], 0, 0, 0);
-                    } else if constexpr (C::DT == Dt::F16) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8, b[j][0]), __builtin_bit_cast(f16x8, a[i][0]),
-                            acc[i][j], 0, 0, 0);
-                    } else {
-                        i32x8 av, bv;
-                        av[0] = a[i][0][0]; av[1] = a[i][0][1]; av[2] = a[i][0][2]; av[3] = a[i][0][3];
-                        av[4] = a[i][1][0]; av[5] = a[i][1][1]; av[6] = a[i][1][2]; av[7] = a[i][1][3];
-                        bv[0] = b[j][0][0]; bv[1] = b[j][0][1]; bv[2] = b[j][0][2]; bv[3] = b[j][0][3];
-                        bv[4] = b[j][1][0]; bv[5] = b[j][1][1]; bv[6] = b[j][1][2]; bv[7] = b[j][1][3];
-                        // formats 0/0 = FP8 e4m3 for both operands; E8M0 scales of
-                        // 2^0 (127): the per-tensor FP32 scales go into alpha
-                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            bv, av, acc[i][j], 0, 0, 0, 127, 0, 127);
-                    }
-                }
-        }
+        for (int j = 0; j < C::FN; ++j) f.b[j][s] = *(const u32x4 *)(ldsB + lds_off(brow + j * C::MT, c));
     }
+}
+
+__device__ __forceinline__ double lo_d(const u32x4 &x) { return u2d((uint64_t)x[0] | ((uint64_t)x[1] << 32)); }
+__device__ __forceinline__ double hi_d(const u32x4 &x) { return u2d((uint64_t)x[2] | ((uint64_t)x[3] << 32)); }
+
+// One k-step of MFMAs.  ZERO: the accumulators start from the constant 0
+// (the first k-step of a segment), so they need no separate clearing.
+template <class C, bool ZERO>
+__device__ __forceinline__ void mfma_step(typename C::Frag (&acc)[C::FM][C::FN], const Frag<C> &f) {
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) {
+            const typename C::Frag cin = ZERO ? typename C::Frag{} : acc[i][j];
+            if constexpr (C::DT == Dt::F64) {
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(lo_d(f.a[i][0]), lo_d(f.b[j][0]), cin, 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(hi_d(f.a[i][0]), hi_d(f.b[j][0]), acc[i][j], 0, 0, 0);
+            } else if constexpr (C::DT == Dt::BF16) {
+                // D = B_frag * A_frag: the transposed block (see the output layout)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, f.b[j][0]), __builtin_bit_cast(bf16x8, f.a[i][0]), cin, 0, 0, 0);
+            } else if constexpr (C::DT == Dt::F16) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(f16x8, f.b[j][0]), __builtin_bit_cast(f16x8, f.a[i][0]), cin, 0, 0, 0);
+            } else {
+                const i32x8 av = __builtin_shufflevector(__builtin_bit_cast(i32x4, f.a[i][0]),
+                                                         __builtin_bit_cast(i32x4, f.a[i][1]), 0, 1, 2, 3, 4, 5, 6, 7);
+                const i32x8 bv = __builtin_shufflevector(__builtin_bit_cast(i32x4, f.b[j][0]),
+                                                         __builtin_bit_cast(i32x4, f.b[j][1]), 0, 1, 2, 3, 4, 5, 6, 7);
+                // formats 0/0 = FP8 e4m3 for both operands; E8M0 scales of
+                // 2^0 (127): the per-tensor FP32 scales go into alpha
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bv, av, cin, 0, 0, 0, 127, 0, 127);
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
 // The MAC loop over iterations [it0, it1) of one tile (Algorithm 3)
+//
+// Per k-tile: the global loads of the next k-tile are issued first; the
+// k-steps run with their operand fragments double-buffered in registers
+// (the reads of step s+1 overlap the MFMAs of step s); the staged next
+// k-tile is written to the other LDS buffer; one barrier; then the first
+// fragments of the next k-tile are read.
 // ---------------------------------------------------------------------------
 template <class C>
 struct Ctx {
@@ -313,15 +332,60 @@ struct Ctx {
     Stage<C, C::BN, C::BKC> sb;
 };
 
+// One k-tile: k-steps with double-buffered fragments, then the staged next
+// k-tile goes to the other LDS buffer, one barrier, and the next k-tile's
+// first fragments are read.  FIRST: the segment's first k-tile, whose first
+// k-step starts the accumulators from zero.
+template <class C, bool FIRST>
+__device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
+                                      char *lds, int it, int it0, int it1, bool rows_in, int kfull, int K,
+                                      uint32_t arow, uint32_t brow, int q) {
+    constexpr int NSUB = Frag<C>::NSUB;
+    const int cur = (it - it0) & 1;
+    const bool more = it + 1 < it1;
+    if (more) {
+        const bool in = rows_in && it + 1 < kfull;
+        cx.sa.load(it + 1, K, in);
+        cx.sb.load(it + 1, K, in);
+    }
+    const char *st = lds + cur * C::STAGE;
+    char *nx = lds + (cur ^ 1) * C::STAGE;
+#pragma unroll
+    for (int ks = 0; ks < NSUB; ++ks) {
+        if (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
+        if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
+        else mfma_step<C, false>(acc, f[ks & 1]);
+    }
+    if (more) {
+        cx.sa.store(nx);
+        cx.sb.store(nx + C::A_BYTES);
+    }
+    __syncthreads();
+    if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
+}
+
 template <class C>
 __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int it0, int it1,
                                          typename C::Frag (&acc)[C::FM][C::FN], char *lds, int tid) {
+    if (it0 >= it1) {
+        // an empty range (not produced by the planner, which never emits
+        // k == 0 work): zero accumulators via a zero-operand k-step
+        Frag<C> z;
 #pragma unroll
-    for (int i = 0; i < C::FM; ++i)
+        for (int s = 0; s < Frag<C>::CPM; ++s) {
 #pragma unroll
-        for (int j = 0; j < C::FN; ++j) acc[i][j] = typename C::Frag{};
-    if (it0 >= it1) return;
+            for (int i = 0; i < C::FM; ++i) z.a[i][s] = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int j = 0; j < C::FN; ++j) z.b[j][s] = u32x4{0u, 0u, 0u, 0u};
+        }
+        mfma_step<C, true>(acc, z);
+        return;
+    }
+    static_assert(Frag<C>::NSUB % 2 == 0, "fragment double buffer needs an even step count");
     const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+    const int q = C::MT == 16 ? (lane >> 4) : (lane >> 5);
+    const uint32_t arow = (uint32_t)(wm * C::WTM + (lane % C::MT));
+    const uint32_t brow = (uint32_t)(wn * C::WTN + (lane % C::MT));
     const int row0 = tm * C::BM, col0 = tn * C::BN;
     Ctx<C> cx;
     cx.sa.init(P.A, P.lda, row0, P.m, tid);
@@ -336,23 +400,11 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
         cx.sb.store(lds + C::A_BYTES);
     }
     __syncthreads();
-    for (int it = it0; it < it1; ++it) {
-        const int cur = (it - it0) & 1;
-        const bool more = it + 1 < it1;
-        if (more) {
-            const bool in = rows_in && it + 1 < kfull;
-            cx.sa.load(it + 1, P.k, in);
-            cx.sb.load(it + 1, P.k, in);
-        }
-        char *st = lds + cur * C::STAGE;
-        mma_ktile<C>(acc, st, st + C::A_BYTES, lane, wm, wn);
-        if (more) {
-            char *nx = lds + (cur ^ 1) * C::STAGE;
-            cx.sa.store(nx);
-            cx.sb.store(nx + C::A_BYTES);
-        }
-        __syncthreads();
-    }
+    Frag<C> f[2];
+    read_frags<C>(f[0], lds, lds + C::A_BYTES, arow, brow, 0, q);
+    ktile<C, true>(cx, f, acc, lds, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+    for (int it = it0 + 1; it < it1; ++it)
+        ktile<C, false>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,18 +483,60 @@ __device__ __forceinline__ void put4(char *p, const Acc (&v)[4], Acc beta, bool 
     (void)EB;
 }
 
-// C_tile = alpha * acc + beta * C_tile (C read only when beta != 0), then
-// rounded once to the output type.  Interior tiles of a C whose rows are
-// 16-byte aligned use 4-wide vector accesses; edge tiles test every element.
+// Partial tiles: thread-fragment order, 16-byte chunk v of thread t at
+// slot + (v*THREADS + t)*16, so stores and loads are fully coalesced.
+template <class C>
+struct PartialLayout {
+    static constexpr int PER = 16 / (int)sizeof(typename C::Acc);   // accumulators per chunk
+    static constexpr int CPF = C::FRAG_N / PER;                      // chunks per fragment
+    __device__ static __forceinline__ int64_t off(int i, int j, int s, int tid) {
+        return ((int64_t)((i * C::FN + j) * CPF + s) * THREADS + tid) * 16;
+    }
+};
+
+// One fragment of a partial tile, as a whole vector.
+template <class C>
+__device__ __forceinline__ typename C::Frag load_partial_frag(const char *slot, int i, int j, int tid) {
+    using PL = PartialLayout<C>;
+    if constexpr (PL::PER == 4) {
+        const f32x4 c0 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 0, tid)));
+        const f32x4 c1 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 1, tid)));
+        const f32x4 c2 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 2, tid)));
+        const f32x4 c3 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 3, tid)));
+        const f32x8 lo = __builtin_shufflevector(c0, c1, 0, 1, 2, 3, 4, 5, 6, 7);
+        const f32x8 hi = __builtin_shufflevector(c2, c3, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+    } else {
+        const f64x2 c0 = __builtin_bit_cast(f64x2, *(const u32x4 *)(slot + PL::off(i, j, 0, tid)));
+        const f64x2 c1 = __builtin_bit_cast(f64x2, *(const u32x4 *)(slot + PL::off(i, j, 1, tid)));
+        return __builtin_shufflevector(c0, c1, 0, 1, 2, 3);
+    }
+}
+
+// v + the fragment of the partial tiles in slots [p0, p1], added in
+// ascending slot order.
+template <class C>
+__device__ __forceinline__ typename C::Frag add_peers(typename C::Frag v, const char *slots, int p0, int p1,
+                                                      int i, int j, int tid) {
+    for (int peer = p0; peer <= p1; ++peer)
+        v = v + load_partial_frag<C>(slots + (int64_t)peer * C::SLOT_BYTES, i, j, tid);
+    return v;
+}
+
+// C_tile = alpha * (acc + partials of slots [p0, p1]) + beta * C_tile (C read
+// only when beta != 0), rounded once to the output type.  The accumulators
+// are only read here: each fragment is copied, completed with the peers'
+// partial sums and stored, one fragment at a time.  Interior tiles of a C
+// whose rows are 16-byte aligned use 4-wide vector accesses; edge tiles test
+// every element.
 template <class C, int CT>
 __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
-                                             typename C::Frag (&acc)[C::FM][C::FN], int tid) {
+                                             const typename C::Frag (&acc)[C::FM][C::FN], int tid,
+                                             const char *slots, int p0, int p1) {
     using Acc = typename C::Acc;
     constexpr int EB = CBytes<CT>::v;
     constexpr int G = C::FRAG_N / 4;                 // column groups per fragment
     const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-    const int rowl = tm * C::BM + wm * C::WTM + (lane % C::MT);
-    const int coll = tn * C::BN + wn * C::WTN + 4 * (lane / C::MT);
     const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
     const bool rd = P.beta != 0.0;
     const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
@@ -452,37 +546,37 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
         // consecutive bytes of one row
         const int r0 = tm * C::BM + wm * C::WTM + (lane >> 4);
         const int c0 = tn * C::BN + wn * C::WTN + (lane & 15);
+        static_for<C::FM * C::FN>([&](auto ij) {
+            constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
+            const typename C::Frag v = add_peers<C>(acc[i][j], slots, p0, p1, i, j, tid);
 #pragma unroll
-        for (int i = 0; i < C::FM; ++i) {
-#pragma unroll
-            for (int j = 0; j < C::FN; ++j) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = r0 + i * 16 + 4 * r, col = c0 + j * 16;
-                    if (interior || (row < P.m && col < P.n)) {
-                        char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
-                        Acc w = alpha * acc[i][j][r];
-                        if (rd) w = w + beta * load_c<CT, Acc>(q);
-                        put_c<CT, Acc>(q, w);
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + i * 16 + 4 * r, col = c0 + j * 16;
+                if (interior || (row < P.m && col < P.n)) {
+                    char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+                    Acc w = alpha * v[r];
+                    if (rd) w = w + beta * load_c<CT, Acc>(q);
+                    put_c<CT, Acc>(q, w);
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
-        }
+            __builtin_amdgcn_sched_barrier(0);
+        });
         return;
     }
-#pragma unroll
-    for (int i = 0; i < C::FM; ++i) {
+    const int rowl = tm * C::BM + wm * C::WTM + (lane % C::MT);
+    const int coll = tn * C::BN + wn * C::WTN + 4 * (lane / C::MT);
+    static_for<C::FM * C::FN>([&](auto ij) {
+        constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
         const int row = rowl + i * C::MT;
         char *rp = (char *)P.C + ((int64_t)row * P.ldc + coll) * EB;
-#pragma unroll
-        for (int j = 0; j < C::FN; ++j) {
+        {
+            const typename C::Frag f = add_peers<C>(acc[i][j], slots, p0, p1, i, j, tid);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int co = j * C::MT + 8 * g;         // column offset from coll
                 Acc v[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = alpha * acc[i][j][4 * g + e];
+                for (int e = 0; e < 4; ++e) v[e] = alpha * f[4 * g + e];
                 if (fast) {
                     put4<CT, Acc>(rp + co * EB, v, beta, rd);
                 } else if (row < P.m) {
@@ -499,38 +593,34 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-    }
+    });
 }
 
 template <class C>
 __device__ __forceinline__ void store_tile(const Problem &P, int tm, int tn,
-                                           typename C::Frag (&acc)[C::FM][C::FN], int tid) {
+                                           const typename C::Frag (&acc)[C::FM][C::FN], int tid,
+                                           const char *slots = nullptr, int p0 = 0, int p1 = -1) {
     if constexpr (C::DT == Dt::F64) {
-        store_tile_t<C, SK_F64>(P, tm, tn, acc, tid);
+        store_tile_t<C, SK_F64>(P, tm, tn, acc, tid, slots, p0, p1);
     } else {
         switch (P.c_type) {
-        case SK_F32: store_tile_t<C, SK_F32>(P, tm, tn, acc, tid); break;
-        case SK_F16: store_tile_t<C, SK_F16>(P, tm, tn, acc, tid); break;
-        default: store_tile_t<C, SK_BF16>(P, tm, tn, acc, tid); break;
+        case SK_F32: store_tile_t<C, SK_F32>(P, tm, tn, acc, tid, slots, p0, p1); break;
+        case SK_F16: store_tile_t<C, SK_F16>(P, tm, tn, acc, tid, slots, p0, p1); break;
+        default: store_tile_t<C, SK_BF16>(P, tm, tn, acc, tid, slots, p0, p1); break;
         }
     }
 }
 
-// Partial tiles: thread-fragment order, 16-byte chunk v of thread t at
-// slot + (v*THREADS + t)*16, so stores and loads are fully coalesced.
 template <class C>
-__device__ __forceinline__ void store_partial(char *slot, typename C::Frag (&acc)[C::FM][C::FN], int tid) {
-    constexpr int PER = 16 / (int)sizeof(typename C::Acc);   // accumulators per chunk
-    constexpr int CPF = C::FRAG_N / PER;                      // chunks per fragment
+__device__ __forceinline__ void store_partial(char *slot, const typename C::Frag (&acc)[C::FM][C::FN], int tid) {
+    using PL = PartialLayout<C>;
+    static_for<C::FM * C::FN>([&](auto ij) {
+        constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
+        {
 #pragma unroll
-    for (int i = 0; i < C::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::FN; ++j)
-#pragma unroll
-            for (int s = 0; s < CPF; ++s) {
-                const int v = (i * C::FN + j) * CPF + s;
+            for (int s = 0; s < PL::CPF; ++s) {
                 u32x4 w;
-                if constexpr (PER == 4) {
+                if constexpr (PL::PER == 4) {
                     w[0] = f2u(acc[i][j][4 * s + 0]);
                     w[1] = f2u(acc[i][j][4 * s + 1]);
                     w[2] = f2u(acc[i][j][4 * s + 2]);
@@ -541,34 +631,11 @@ __device__ __forceinline__ void store_partial(char *slot, typename C::Frag (&acc
                     w[0] = (uint32_t)x0; w[1] = (uint32_t)(x0 >> 32);
                     w[2] = (uint32_t)x1; w[3] = (uint32_t)(x1 >> 32);
                 }
-                *(u32x4 *)(slot + ((int64_t)v * THREADS + tid) * 16) = w;
-                if (s == CPF - 1) __builtin_amdgcn_sched_barrier(0);
+                *(u32x4 *)(slot + PL::off(i, j, s, tid)) = w;
             }
-}
-
-template <class C>
-__device__ __forceinline__ void add_partial(const char *slot, typename C::Frag (&acc)[C::FM][C::FN], int tid) {
-    constexpr int PER = 16 / (int)sizeof(typename C::Acc);
-    constexpr int CPF = C::FRAG_N / PER;
-#pragma unroll
-    for (int i = 0; i < C::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::FN; ++j)
-#pragma unroll
-            for (int s = 0; s < CPF; ++s) {
-                const int v = (i * C::FN + j) * CPF + s;
-                const u32x4 w = *(const u32x4 *)(slot + ((int64_t)v * THREADS + tid) * 16);
-                if constexpr (PER == 4) {
-                    acc[i][j][4 * s + 0] += u2f(w[0]);
-                    acc[i][j][4 * s + 1] += u2f(w[1]);
-                    acc[i][j][4 * s + 2] += u2f(w[2]);
-                    acc[i][j][4 * s + 3] += u2f(w[3]);
-                } else {
-                    acc[i][j][2 * s + 0] += u2d((uint64_t)w[0] | ((uint64_t)w[1] << 32));
-                    acc[i][j][2 * s + 1] += u2d((uint64_t)w[2] | ((uint64_t)w[3] << 32));
-                }
-                if (s == CPF - 1) __builtin_amdgcn_sched_barrier(0);
-            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -727,12 +794,12 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         if (!ended) {
             const int li = t1 - 1;
             last = li < rq ? li / (q + 1) : r + (li - rq) / q;
-            for (int peer = x + 1; peer <= last; ++peer) {
+            for (int peer = x + 1; peer <= last; ++peer)
                 wait_flag(p.flags + peer * FLAG_STRIDE, p.err, p.spin_limit, tid);
-                add_partial<C>((const char *)p.partials + (int64_t)peer * C::SLOT_BYTES, acc, tid);
-            }
         }
-        store_tile<C>(*tr.P, tm, tn, acc, tid);
+        // peers' partial tiles are added in ascending slot order inside the
+        // epilogue, fragment by fragment
+        store_tile<C>(*tr.P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last);
         trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER),
                   last, tid);
     }

@@ -21,6 +21,9 @@ class Workspace:
     def ensure(self, nbytes: int) -> None:
         if nbytes > self.buf.numel():
             self.buf = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+            # the zero fill runs on the current stream; a launch on another
+            # stream must not see the buffer before it is clear
+            torch.cuda.current_stream(self.device).synchronize()
 
     @property
     def ptr(self) -> int:

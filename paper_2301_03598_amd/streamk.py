@@ -11,7 +11,7 @@ import os
 from ctypes import c_double, c_float, c_int32, c_int64, c_uint64, c_void_p, c_char_p
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstreamk.so")
+LIB_PATH = os.environ.get("STREAMK_LIB") or os.path.join(_HERE, "libstreamk.so")
 
 # status codes
 SK_OK, SK_ERR_INVALID_VALUE, SK_ERR_UNSUPPORTED, SK_ERR_WORKSPACE_TOO_SMALL, \

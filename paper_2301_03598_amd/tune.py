@@ -1,0 +1,213 @@
+"""Autotuner and grid-model calibration for the Stream-K library.
+
+Baseline (the paper, section 5.1 and appendix A.1): one tile per precision,
+the two-tile SK + DP hybrid, and the grid size of basic Stream-K chosen by
+the analytical model time(g) = a + b[peers > 1] + c*ItersPerCta(g)
++ d*(peers - 1) with constants measured once per architecture.
+
+This module
+* measures the model constants (a, b, c, d) per (dtype, tile) on the device
+  from timed basic-Stream-K launches and fits them by least squares
+  (``calibrate``); the results are compiled into the library's defaults;
+* searches tile x schedule x grid x hybrid threshold per (dtype, shape
+  bucket) or per grouped batch and caches the winners in a JSON file
+  (``Tuner``).  Every candidate runs through the C ABI; timing uses HIP
+  events on the launch stream.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import asdict, dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import runtime as R
+from . import streamk as S
+
+TILES = {"f64": [(128, 128, 16), (64, 64, 16)],
+         "f16": [(256, 256, 64), (128, 128, 64)],
+         "bf16": [(256, 256, 64), (128, 128, 64)],
+         "f8e4m3": [(256, 256, 128), (128, 128, 128)]}
+CTYPE = {"f64": "f64", "f16": "f32", "bf16": "f32", "f8e4m3": "f32"}
+
+
+@dataclass
+class Choice:
+    sched: str
+    blk: Tuple[int, int, int]
+    grid: int = 0
+    threshold: int = 0
+    us: float = 0.0
+
+    def config(self, **extra) -> S.sk_config_t:
+        return S.make_config(sched=self.sched, blk=self.blk, grid=self.grid, threshold=self.threshold, **extra)
+
+
+def _time_us(fn, reps: int = 5, warm: int = 2) -> float:
+    for _ in range(warm):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+class _Operands:
+    """Device operands for timing one shape (values irrelevant to timing)."""
+
+    def __init__(self, ab, ct, m, n, k, gen):
+        from workloads import torch_dtype
+        self.A = torch.empty(m * k, dtype=torch_dtype(ab), device="cuda")
+        self.B = torch.empty(k * n, dtype=torch_dtype(ab), device="cuda")
+        if ab == "f8e4m3":
+            self.A.copy_(torch.randn(m * k, device="cuda", generator=gen).to(torch.float8_e4m3fn))
+            self.B.copy_(torch.randn(k * n, device="cuda", generator=gen).to(torch.float8_e4m3fn))
+        else:
+            self.A.uniform_(-1, 1, generator=gen)
+            self.B.uniform_(-1, 1, generator=gen)
+        self.C = torch.empty(m * n, dtype=torch_dtype(ct), device="cuda")
+        self.desc = S.make_desc(m, n, k, self.A, self.B, self.C, ab_type=ab, c_type=ct)
+
+
+def _run(desc, cfg, ws: R.Workspace, grouped: bool = False, count: int = 1):
+    stream = torch.cuda.current_stream().cuda_stream
+    if grouped:
+        S.check(S.sk_gemm_grouped(desc, cfg, ws.ptr, ws.nbytes, stream), "sk_gemm_grouped")
+    else:
+        S.check(S.sk_gemm(desc, cfg, ws.ptr, ws.nbytes, stream), "sk_gemm")
+
+
+def measure(desc, cfg, ws: R.Workspace, reps: int = 5, grouped: bool = False) -> Optional[float]:
+    st, plan = S.sk_plan(desc, cfg)
+    if st != S.SK_OK:
+        return None
+    ws.ensure(plan.workspace_bytes)
+    return _time_us(lambda: _run(desc, cfg, ws, grouped), reps)
+
+
+# ---------------------------------------------------------------------------
+# grid-model calibration (appendix A.1)
+# ---------------------------------------------------------------------------
+
+def calibrate(ab: str, blk: Tuple[int, int, int], shapes: Sequence[Tuple[int, int, int]] = (),
+              grids: Sequence[int] = (), seed: int = 0) -> Dict[str, float]:
+    """Fit (a, b, c, d) in microseconds from basic-Stream-K timings."""
+    import numpy as np
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    bm, bn, bk = blk
+    if not shapes:
+        shapes = [(bm, bn, bk * 512), (2 * bm, 2 * bn, bk * 128), (4 * bm, 2 * bn, bk * 64),
+                  (bm, 8 * bn, bk * 256)]
+    ws = R.Workspace("cuda")
+    rows, ys = [], []
+    for (m, n, k) in shapes:
+        ops = _Operands(ab, CTYPE[ab], m, n, k, gen)
+        T = -(-m // bm) * -(-n // bn) * -(-k // bk)
+        I = -(-k // bk)
+        gs = grids or sorted({g for g in (1, 2, 4, 8, 16, 32, 64, 128, 192, 256) if g <= T})
+        for g in gs:
+            cfg = S.make_config(sched="sk", blk=blk, grid=g)
+            us = measure(ops.desc, cfg, ws)
+            if us is None:
+                continue
+            ipc = -(-T // g)
+            peers = -(-I // ipc)
+            rows.append([1.0, 1.0 if peers > 1 else 0.0, float(ipc), float(peers - 1)])
+            ys.append(us)
+    X, y = np.array(rows), np.array(ys)
+    coef, *_ = np.linalg.lstsq(X, y, rcond=None)
+    a, b, c, d = (float(v) for v in coef)
+    return {"a": a, "b": max(b, 0.0), "c": max(c, 1e-3), "d": max(d, 0.0), "samples": len(ys),
+            "rms_us": float(np.sqrt(np.mean((X @ coef - y) ** 2)))}
+
+
+# ---------------------------------------------------------------------------
+# the autotuner
+# ---------------------------------------------------------------------------
+
+def bucket(ab: str, m: int, n: int, k: int) -> str:
+    f = lambda v: int(round(math.log2(max(v, 1))))
+    return f"{ab}:{f(m)}:{f(n)}:{f(k)}"
+
+
+class Tuner:
+    """Per-(dtype, shape bucket) best configuration, cached in JSON."""
+
+    def __init__(self, path: Optional[str] = None):
+        self.path = path
+        self.table: Dict[str, dict] = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.table = json.load(f)
+        self.ws = R.Workspace("cuda")
+
+    def save(self):
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+    @staticmethod
+    def candidates(ab: str, slots: Optional[Dict[Tuple[int, int, int], int]] = None) -> List[Choice]:
+        out = []
+        for blk in TILES[ab]:
+            p = (slots or {}).get(blk, 256)
+            out.append(Choice("dp", blk))
+            out.append(Choice("auto", blk))
+            out.append(Choice("dp1sk", blk))
+            out.append(Choice("2tsk", blk, threshold=1))
+            for g in sorted({0, p // 4, p // 2, p}):
+                out.append(Choice("sk", blk, grid=g))
+        return out
+
+    def _slots(self, ab: str, desc) -> Dict[Tuple[int, int, int], int]:
+        res = {}
+        for blk in TILES[ab]:
+            st, pl = S.sk_plan(desc, S.make_config(sched="sk", blk=blk))
+            if st == S.SK_OK:
+                res[blk] = pl.wg_slots
+        return res
+
+    def tune(self, ab: str, m: int, n: int, k: int, reps: int = 5, seed: int = 0) -> Choice:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        ops = _Operands(ab, CTYPE[ab], m, n, k, gen)
+        return self._search(ops.desc, ab, bucket(ab, m, n, k), reps, grouped=False)
+
+    def tune_grouped(self, descs, ab: str, key: str, reps: int = 3) -> Choice:
+        arr = (S.sk_gemm_desc_t * len(descs))(*descs)
+        return self._search(arr, ab, key, reps, grouped=True)
+
+    def _search(self, desc, ab, key, reps, grouped) -> Choice:
+        first = desc[0] if grouped else desc
+        best: Optional[Choice] = None
+        base_us = None
+        for ch in self.candidates(ab, self._slots(ab, first)):
+            us = measure(desc, ch.config(), self.ws, reps, grouped)
+            if us is None:
+                continue
+            if ch.sched == "auto" and ch.blk == TILES[ab][0]:
+                base_us = us
+            if best is None or us < best.us:
+                best = Choice(ch.sched, ch.blk, ch.grid, ch.threshold, us)
+        assert best is not None
+        self.table[key] = dict(asdict(best), baseline_us=base_us)
+        return best
+
+    def lookup(self, ab: str, m: int, n: int, k: int) -> Optional[Choice]:
+        e = self.table.get(bucket(ab, m, n, k))
+        if not e:
+            return None
+        return Choice(e["sched"], tuple(e["blk"]), e["grid"], e["threshold"], e["us"])
+
+    def config_for(self, ab: str, m: int, n: int, k: int) -> S.sk_config_t:
+        ch = self.lookup(ab, m, n, k)
+        return ch.config() if ch else S.make_config()
