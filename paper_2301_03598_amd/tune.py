@@ -211,3 +211,22 @@ class Tuner:
     def config_for(self, ab: str, m: int, n: int, k: int) -> S.sk_config_t:
         ch = self.lookup(ab, m, n, k)
         return ch.config() if ch else S.make_config()
+
+
+def main():
+    """python -m paper_2301_03598_amd.tune calibrate|sweep-buckets"""
+    import sys
+    what = sys.argv[1] if len(sys.argv) > 1 else "calibrate"
+    if what == "calibrate":
+        out = {}
+        for ab in ("f16", "bf16", "f8e4m3", "f64"):
+            for blk in TILES[ab]:
+                out[f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}"] = calibrate(ab, blk)
+                print(json.dumps({f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}": out[f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}"]}),
+                      flush=True)
+    else:
+        raise SystemExit(f"unknown command {what}")
+
+
+if __name__ == "__main__":
+    main()
