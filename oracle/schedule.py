@@ -222,8 +222,10 @@ class Problems:
 
 def plan_problems(probs: Problems, p: int, sched: int, grid: int = 0,
                   consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2) -> Plan:
-    return make_plan(probs.tiles, probs.region_iters, max(probs.Ip) if probs.Ip else 0,
-                     p, sched, grid, consts, threshold)
+    # the model's per-tile iteration count is that of the deepest tile that
+    # exists: a problem with no output tiles has no MAC-loop iterations
+    depth = max((I for t, I in zip(probs.tp, probs.Ip) if t > 0), default=0)
+    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold)
 
 
 def segments(probs: Problems, plan: Plan) -> List[List[Segment]]:
