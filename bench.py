@@ -180,7 +180,7 @@ def schedule_leg(sweep, sched, passes=2):
             "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, warm + durs
 
 
-def cpu_baseline(budget_flops=1.2e11):
+def cpu_baseline(budget_flops=7.0e11):
     """The CPU oracle, as it stands, on a bounded sample of the sweep: the
     problems in draw order whose flops fit the budget, FP16 inputs."""
     import oracle

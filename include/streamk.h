@@ -126,7 +126,8 @@ typedef struct {
     int64_t trace_capacity;
 } sk_config_t;
 
-#define SK_FLAG_NO_XCD_REMAP 0x1   /* keep logical workgroup id == hardware id */
+#define SK_FLAG_NO_XCD_REMAP 0x1     /* keep logical workgroup id == hardware id */
+#define SK_FLAG_ROW_MAJOR_TILES 0x2  /* tile t -> (t / tiles_n, t % tiles_n) instead of banded order */
 
 /* The resolved launch plan of a call (host only; no device access when
  * cfg->wg_slots > 0). */

@@ -15,6 +15,7 @@ struct Problem {
     void *C;
     int64_t lda, ldb, ldc;   // elements
     int32_t m, n, k;
+    int32_t tiles_m;         // ceil(m / BM)
     int32_t tiles_n;         // ceil(n / BN)
     int32_t iters;           // ceil(k / BK): MAC-loop iterations per tile
     int32_t c_type;          // sk_dtype_t of C
@@ -31,7 +32,6 @@ __host__ __device__ inline int dtype_bytes(int t) {
 // column-major-C case becomes C^T = B^T A^T with a row-major C^T).
 // Operand contiguity is preserved by the swap: see a_kcontig / b_kcontig.
 __host__ __device__ inline Problem to_problem(const sk_gemm_desc_t &d, int bm, int bn, int bk) {
-    (void)bm;
     Problem p;
     const bool swap = d.c_order == SK_COL_MAJOR;
     const int64_t lda = d.lda ? d.lda : (d.a_order == SK_ROW_MAJOR ? d.k : d.m);
@@ -47,6 +47,7 @@ __host__ __device__ inline Problem to_problem(const sk_gemm_desc_t &d, int bm, i
     p.C = d.C;
     p.ldc = ldc;
     p.k = (int32_t)d.k;
+    p.tiles_m = (p.m + bm - 1) / bm;
     p.tiles_n = (p.n + bn - 1) / bn;
     p.iters = (p.k + bk - 1) / bk;
     p.c_type = d.c_type;
@@ -87,6 +88,7 @@ struct Params {
     int32_t dp_tiles;        // tiles outside the SK region
     int32_t dp_first;
     int32_t xcd_remap;
+    int32_t band;            // tile rasterisation band (1: row-major tiles)
     int32_t spin_limit;      // bounded fixup wait (polls)
     void *partials;          // g slots of BM*BN accumulators
     int32_t *flags;          // g flags, FLAG_STRIDE ints apart

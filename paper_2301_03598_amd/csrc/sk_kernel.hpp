@@ -101,6 +101,11 @@ struct Cfg {
     static constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
     static constexpr int STAGE = A_BYTES + B_BYTES;
     static constexpr int LDS = 2 * STAGE;
+    // register staging sets: with two, the global loads of k-tile i+2 are
+    // issued while k-tile i+1 (loaded one k-tile earlier) goes to LDS, so a
+    // load has about two k-tiles of MFMA work to arrive.  The 256x256 FP8
+    // tile has no registers to spare for the second set.
+    static constexpr int RSETS = (D == Dt::F8 && BM >= 256) ? 1 : 2;
     using Acc = typename DtTraits<D>::Acc;
     using Frag = typename DtTraits<D>::Frag;
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
@@ -148,7 +153,7 @@ struct Stage {
     bool mn_valid;         // !KC: this thread's mn block lies inside the matrix
     int kofs;              // k offset (elements) of this thread's first load within a k-tile
     uint32_t lds0;         // LDS offset of the first store (KC) / row base (!KC)
-    u32x4 r[NL];
+    u32x4 r[C::RSETS][NL];
 
     static constexpr uint32_t OOB = 0x80000000u;
 
@@ -177,7 +182,8 @@ struct Stage {
         }
     }
 
-    // Issue the loads of k-tile kt.  Out-of-range data are zero.
+    // Issue the loads of k-tile kt into register set S.  Out-of-range data are zero.
+    template <int S>
     __device__ __forceinline__ void load(int kt, int K, bool interior) {
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
@@ -186,28 +192,31 @@ struct Stage {
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 const uint32_t o = (interior || (kv && i < rows_valid)) ? voff : OOB;
-                r[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, i * ustride, 0));
+                r[S][i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, i * ustride, 0));
             }
         } else {
             const int k0 = kt * BK + kofs;
 #pragma unroll
             for (int j = 0; j < NL; ++j) {
                 const uint32_t o = (interior || (mn_valid && k0 + j < K)) ? voff : OOB;
-                r[j] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, j * ustride, 0));
+                r[S][j] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, j * ustride, 0));
             }
         }
     }
 
-    // element e (0..VEC-1) of loaded vector j, as raw bits in the low E bytes
+    // element e (0..VEC-1) of loaded vector j of set S, as raw bits in the low E bytes
+    template <int S>
     __device__ __forceinline__ uint32_t elem_bits(int j, int e) const {
-        if constexpr (E == 2) return (r[j][e >> 1] >> ((e & 1) * 16)) & 0xffffu;
-        else return (r[j][e >> 2] >> ((e & 3) * 8)) & 0xffu;
+        if constexpr (E == 2) return (r[S][j][e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+        else return (r[S][j][e >> 2] >> ((e & 3) * 8)) & 0xffu;
     }
 
+    // Write register set S to an LDS stage.
+    template <int S>
     __device__ __forceinline__ void store(char *lds) const {
         if constexpr (KC) {
 #pragma unroll
-            for (int i = 0; i < NL; ++i) *(u32x4 *)(lds + lds0 + i * 32 * 128) = r[i];
+            for (int i = 0; i < NL; ++i) *(u32x4 *)(lds + lds0 + i * 32 * 128) = r[S][i];
         } else {
             const int kb_byte = kofs * E;               // byte offset of the piece in a row
 #pragma unroll
@@ -218,10 +227,10 @@ struct Stage {
 #pragma unroll
                     for (int s = 0; s < PIECE / 16; ++s) {
                         u32x4 w;
-                        w[0] = r[2 * s][2 * e];
-                        w[1] = r[2 * s][2 * e + 1];
-                        w[2] = r[2 * s + 1][2 * e];
-                        w[3] = r[2 * s + 1][2 * e + 1];
+                        w[0] = r[S][2 * s][2 * e];
+                        w[1] = r[S][2 * s][2 * e + 1];
+                        w[2] = r[S][2 * s + 1][2 * e];
+                        w[3] = r[S][2 * s + 1][2 * e + 1];
                         *(u32x4 *)(lds + lds_off(row, (kb_byte >> 4) + s)) = w;
                     }
                 } else {
@@ -232,7 +241,7 @@ struct Stage {
                     for (int q = 0; q < NW; ++q) {
                         uint32_t v = 0;
 #pragma unroll
-                        for (int b = 0; b < PER; ++b) v |= elem_bits(q * PER + b, e) << (b * 8 * E);
+                        for (int b = 0; b < PER; ++b) v |= elem_bits<S>(q * PER + b, e) << (b * 8 * E);
                         w[q] = v;
                     }
                     char *dst = lds + lds_off(row, kb_byte >> 4) + (kb_byte & 15);
@@ -320,11 +329,12 @@ __device__ __forceinline__ void mfma_step(typename C::Frag (&acc)[C::FM][C::FN],
 // ---------------------------------------------------------------------------
 // The MAC loop over iterations [it0, it1) of one tile (Algorithm 3)
 //
-// Per k-tile: the global loads of the next k-tile are issued first; the
-// k-steps run with their operand fragments double-buffered in registers
-// (the reads of step s+1 overlap the MFMAs of step s); the staged next
-// k-tile is written to the other LDS buffer; one barrier; then the first
-// fragments of the next k-tile are read.
+// Per k-tile i: the global loads of k-tile i + RSETS are issued first (into
+// the register set that k-tile i came through); the k-steps run with their
+// operand fragments double-buffered in registers (the reads of step s+1
+// overlap the MFMAs of step s); k-tile i+1, already in registers, is written
+// to the other LDS buffer; one barrier; then the first fragments of k-tile
+// i+1 are read.
 // ---------------------------------------------------------------------------
 template <class C>
 struct Ctx {
@@ -332,21 +342,24 @@ struct Ctx {
     Stage<C, C::BN, C::BKC> sb;
 };
 
-// One k-tile: k-steps with double-buffered fragments, then the staged next
-// k-tile goes to the other LDS buffer, one barrier, and the next k-tile's
-// first fragments are read.  FIRST: the segment's first k-tile, whose first
-// k-step starts the accumulators from zero.
-template <class C, bool FIRST>
+// One k-tile.  FIRST: the segment's first k-tile, whose first k-step starts
+// the accumulators from zero.  P: parity of the k-tile within the segment,
+// which selects the register set loaded now (and, with two sets, the other
+// one is written to LDS).
+template <class C, bool FIRST, int P>
 __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
                                       char *lds, int it, int it0, int it1, bool rows_in, int kfull, int K,
                                       uint32_t arow, uint32_t brow, int q) {
     constexpr int NSUB = Frag<C>::NSUB;
+    constexpr int LD = C::RSETS == 2 ? P : 0;          // set receiving the new loads
+    constexpr int ST = C::RSETS == 2 ? P ^ 1 : 0;      // set written to LDS
     const int cur = (it - it0) & 1;
     const bool more = it + 1 < it1;
-    if (more) {
-        const bool in = rows_in && it + 1 < kfull;
-        cx.sa.load(it + 1, K, in);
-        cx.sb.load(it + 1, K, in);
+    const int ahead = it + C::RSETS;
+    if (ahead < it1) {
+        const bool in = rows_in && ahead < kfull;
+        cx.sa.template load<LD>(ahead, K, in);
+        cx.sb.template load<LD>(ahead, K, in);
     }
     const char *st = lds + cur * C::STAGE;
     char *nx = lds + (cur ^ 1) * C::STAGE;
@@ -357,8 +370,8 @@ __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::F
         else mfma_step<C, false>(acc, f[ks & 1]);
     }
     if (more) {
-        cx.sa.store(nx);
-        cx.sb.store(nx + C::A_BYTES);
+        cx.sa.template store<ST>(nx);
+        cx.sb.template store<ST>(nx + C::A_BYTES);
     }
     __syncthreads();
     if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
@@ -368,8 +381,9 @@ template <class C>
 __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int it0, int it1,
                                          typename C::Frag (&acc)[C::FM][C::FN], char *lds, int tid) {
     if (it0 >= it1) {
-        // an empty range (not produced by the planner, which never emits
-        // k == 0 work): zero accumulators via a zero-operand k-step
+        // an empty range (never produced by the planner, which sends k == 0
+        // work to the C = beta*C kernel): zero accumulators via a
+        // zero-operand k-step
         Frag<C> z;
 #pragma unroll
         for (int s = 0; s < Frag<C>::CPM; ++s) {
@@ -394,17 +408,31 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
     const int kfull = P.k / C::BK;                 // k-tiles with no k edge
     {
         const bool in = rows_in && it0 < kfull;
-        cx.sa.load(it0, P.k, in);
-        cx.sb.load(it0, P.k, in);
-        cx.sa.store(lds);
-        cx.sb.store(lds + C::A_BYTES);
+        cx.sa.template load<0>(it0, P.k, in);
+        cx.sb.template load<0>(it0, P.k, in);
+        if (C::RSETS == 2 && it0 + 1 < it1) {
+            const bool in1 = rows_in && it0 + 1 < kfull;
+            cx.sa.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
+            cx.sb.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
+        }
+        cx.sa.template store<0>(lds);
+        cx.sb.template store<0>(lds + C::A_BYTES);
     }
     __syncthreads();
     Frag<C> f[2];
     read_frags<C>(f[0], lds, lds + C::A_BYTES, arow, brow, 0, q);
-    ktile<C, true>(cx, f, acc, lds, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-    for (int it = it0 + 1; it < it1; ++it)
-        ktile<C, false>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+    ktile<C, true, 0>(cx, f, acc, lds, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+    if constexpr (C::RSETS == 2) {
+        // k-tiles in pairs so the register-set parity is a constant
+        for (int it = it0 + 1; it < it1; it += 2) {
+            ktile<C, false, 1>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+            if (it + 1 < it1)
+                ktile<C, false, 0>(cx, f, acc, lds, it + 1, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+        }
+    } else {
+        for (int it = it0 + 1; it < it1; ++it)
+            ktile<C, false, 0>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -678,6 +706,41 @@ __device__ __forceinline__ void trace_rec(const Params &p, int wg, int seq, int 
 // ---------------------------------------------------------------------------
 // tile lookup
 // ---------------------------------------------------------------------------
+
+// Output coordinates of a problem's tile t.  The iteration space is linearised
+// tile by tile (m->n->k, section 4); the tile-to-coordinate map is a banded
+// raster: bands of `band` tile rows, each walked column by column, so that a
+// run of consecutive tiles covers a compact block of C and shares A and B
+// panels in cache.  band == 1 is the plain row-major order.
+__device__ __forceinline__ void tile_coords(const Problem &P, int t, int band, int &tm, int &tn) {
+    if (band <= 1) {
+        tm = t / P.tiles_n;
+        tn = t % P.tiles_n;
+        return;
+    }
+    const int per = band * P.tiles_n;
+    const int m0 = (t / per) * band, r = t % per;
+    const int rows = P.tiles_m - m0 < band ? P.tiles_m - m0 : band;
+    tm = m0 + r % rows;
+    tn = r / rows;
+}
+
+// Every field of a unit's problem is the same in all lanes; reading it through
+// readfirstlane states that, so buffer resources and loop bounds derived from
+// it live in scalar registers (a resource the compiler must assume divergent
+// costs a readfirstlane loop around every buffer load).
+__device__ __forceinline__ Problem uniform_problem(const Problem &src) {
+    static_assert(sizeof(Problem) % 4 == 0, "word copy");
+    uint32_t w[sizeof(Problem) / 4];
+    __builtin_memcpy(w, &src, sizeof(Problem));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Problem) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    Problem out;
+    __builtin_memcpy(&out, w, sizeof(Problem));
+    return out;
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 struct TileRef {
     const Problem *P;
     int tile_local;     // tile index within its problem
@@ -729,7 +792,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
     int x = b;
-    if (!DP_ONLY && p.xcd_remap) {
+    if (p.xcd_remap) {
         // hardware dispatches workgroup b to XCD b % 8; give each XCD a
         // contiguous run of logical ids so Stream-K neighbours share an L2
         const int q8 = p.g >> 3, r8 = p.g & 7, j = b & 7;
@@ -763,27 +826,29 @@ __device__ __forceinline__ void sk_body(const Params &p) {
             tile = tile_of_iter<C::GROUPED>(p, p.sk_iter_begin + it);
         }
         const TileRef tr = tile_of_tile<C::GROUPED>(p, tile);
+        const Problem P = uniform_problem(*tr.P);
         int t1 = 0;
         if (dp_now) {
             k0 = 0;
-            k1 = tr.P->iters;
+            k1 = P.iters;
         } else {
-            const int t0 = tr.it_begin - p.sk_iter_begin;   // region-relative tile start
-            t1 = t0 + tr.P->iters;
+            const int t0 = uniform_int(tr.it_begin) - p.sk_iter_begin;   // region-relative tile start
+            t1 = t0 + P.iters;
             k0 = it - t0;
             k1 = (end < t1 ? end : t1) - t0;
             started = it == t0;
             ended = end >= t1;
             it = t1;
         }
-        const int tm = tr.tile_local / tr.P->tiles_n, tn = tr.tile_local % tr.P->tiles_n;
+        int tm, tn;
+        tile_coords(P, uniform_int(tr.tile_local), p.band, tm, tn);
         // an opaque copy of the thread index: per-thread addresses are
         // recomputed for every unit instead of being hoisted out of this loop
         // and kept live (spilled) across the whole kernel
         int tid = tid0;
         asm volatile("" : "+v"(tid));
         typename C::Frag acc[C::FM][C::FN];
-        mac_loop<C>(*tr.P, tm, tn, k0, k1, acc, lds, tid);
+        mac_loop<C>(P, tm, tn, k0, k1, acc, lds, tid);
         if (!started) {
             store_partial<C>((char *)p.partials + (int64_t)x * C::SLOT_BYTES, acc, tid);
             signal_flag(p.flags + x * FLAG_STRIDE, tid);
@@ -799,7 +864,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         }
         // peers' partial tiles are added in ascending slot order inside the
         // epilogue, fragment by fragment
-        store_tile<C>(*tr.P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last);
+        store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last);
         trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER),
                   last, tid);
     }

@@ -21,6 +21,7 @@ SK_F64, SK_F32, SK_F16, SK_BF16, SK_F8_E4M3 = range(5)
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_SCHED_AUTO, SK_SCHED_DP, SK_SCHED_SK, SK_SCHED_DP_1TILE_SK, SK_SCHED_2TILE_SK_DP = range(5)
 SK_FLAG_NO_XCD_REMAP = 0x1
+SK_FLAG_ROW_MAJOR_TILES = 0x2
 
 DTYPE = {"f64": SK_F64, "f32": SK_F32, "f16": SK_F16, "bf16": SK_BF16, "f8e4m3": SK_F8_E4M3}
 ORDER = {"row": SK_ROW_MAJOR, "col": SK_COL_MAJOR}

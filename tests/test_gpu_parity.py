@@ -164,6 +164,18 @@ def test_xcd_remap_off_same_bits(ws):
     assert torch.equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("sched,grid", [("dp", 0), ("sk", 96), ("auto", 0)])
+def test_tile_raster_orders(sched, grid, ws):
+    # banded (default) and row-major tile rasters, with and without the XCD
+    # remap, over 11 x 13 tiles (ragged in both dimensions, not a multiple of
+    # the band): integer-valued data makes every order exact against the oracle
+    m, n, k = 11 * 128 - 40, 13 * 128 - 24, 1024
+    for flags in (0, S.SK_FLAG_ROW_MAJOR_TILES, S.SK_FLAG_NO_XCD_REMAP,
+                  S.SK_FLAG_NO_XCD_REMAP | S.SK_FLAG_ROW_MAJOR_TILES):
+        cfg = S.make_config(sched=sched, blk=(128, 128, 64), grid=grid, flags=flags)
+        check_case(m, n, k, "bf16", "f32", dist="int4", seed=5, cfg=cfg, ws=ws, trace=False)
+
+
 def test_k_zero_and_alpha_zero_scale_c(ws):
     m, n = 100, 64
     rng = np.random.default_rng(1)
