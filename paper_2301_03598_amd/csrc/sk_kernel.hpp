@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "sk_internal.h"
@@ -106,6 +107,10 @@ struct Cfg {
     // load has about two k-tiles of MFMA work to arrive.  The 256x256 FP8
     // tile has no registers to spare for the second set.
     static constexpr int RSETS = (D == Dt::F8 && BM >= 256) ? 1 : 2;
+    // FP16/BF16 operands go global -> LDS directly (LDS-DMA buffer loads);
+    // an operand contiguous along m (n) keeps its natural layout in LDS and
+    // is transposed by the LDS transpose reads that build its fragments.
+    static constexpr bool DMA = D == Dt::F16 || D == Dt::BF16;
     using Acc = typename DtTraits<D>::Acc;
     using Frag = typename DtTraits<D>::Frag;
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
@@ -255,6 +260,92 @@ struct Stage {
 };
 
 // ---------------------------------------------------------------------------
+// global -> LDS staging of one 16-bit operand tile with LDS-DMA loads
+//
+// Each wave instruction moves 1 KiB: lane L's 16 bytes land at the wave's
+// LDS block + 16 L, so the XOR swizzles are applied by choosing which global
+// chunk each lane fetches.
+//  KC (rows x k, k contiguous): the block is 8 rows of 128 bytes in the
+//    lds_off layout; lane L fetches row L/8, chunk (L%8) ^ ((row/2) % 8).
+//  !KC (k x rows, rows contiguous): LDS k-row p holds the tile's ROWS
+//    values (2*ROWS bytes) with 16-byte chunk c at slot c ^ 4(p % 4); the
+//    block is 1024 / (2*ROWS) k-rows.
+// Loads outside the matrix get an offset past the resource range and
+// deposit zeros.
+// ---------------------------------------------------------------------------
+template <class C, int ROWS, bool KC>
+struct StageDma {
+    static constexpr int NL = ROWS / 32;            // loads per wave per k-tile
+    static constexpr int E = C::E, VEC = C::VEC, BK = C::BK;
+    static constexpr int CPR = ROWS / 8;            // !KC: chunks per k-row
+    static constexpr int KR = 1024 / (ROWS * E);    // !KC: k-rows per 1 KiB block
+    static_assert(E == 2 && BK == 64, "16-bit operands, 128-byte k rows");
+    static constexpr uint32_t OOB = 0x80000000u;
+    const char *ub;
+    int64_t ustep;
+    uint32_t ustride;
+    uint32_t voff;
+    int rows_valid;        // KC: number of valid leading loads (row edge)
+    bool mn_valid;         // !KC: this lane's chunk lies inside the matrix
+    int kofs;              // k offset of this lane's first load within a k-tile
+    uint32_t lds_w;        // the wave's first block within the operand stage
+
+    __device__ __forceinline__ void init(const void *ptr, int64_t ld, int row0, int rows_total, int tid) {
+        const char *p = (const char *)ptr;
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6), L = tid & 63;
+        if constexpr (KC) {
+            const int rr = 8 * w + (L >> 3);
+            const int c = (L & 7) ^ ((4 * w + (L >> 4)) & 7);
+            ub = p + (int64_t)row0 * ld * E;
+            ustep = (int64_t)BK * E;
+            ustride = (uint32_t)(32 * ld * E);
+            voff = (uint32_t)(((int64_t)rr * ld + c * VEC) * E);
+            const int rem = rows_total - row0 - rr;
+            rows_valid = rem <= 0 ? 0 : (rem + 31) / 32;
+            kofs = c * VEC;
+            lds_w = (uint32_t)(8 * w * 128);
+        } else {
+            const int pr = w * KR + L / CPR;            // k-row of load 0 within the k-tile
+            const int c = (L % CPR) ^ (4 * (pr & 3));
+            ub = p + (int64_t)row0 * E;
+            ustep = (int64_t)BK * ld * E;
+            ustride = (uint32_t)(4 * KR * ld * E);
+            voff = (uint32_t)(((int64_t)pr * ld + c * VEC) * E);
+            mn_valid = row0 + c * VEC < rows_total;
+            kofs = pr;
+            lds_w = (uint32_t)(w * 1024);
+        }
+    }
+
+    __device__ __forceinline__ void dma(const __amdgpu_buffer_rsrc_t &rs, char *dst, uint32_t o, uint32_t so) const {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16, o, so, 0, 0);
+    }
+
+    // Issue the loads of k-tile kt into the operand stage at `lds`.
+    __device__ __forceinline__ void issue(char *lds, int kt, int K, bool interior) const {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
+        constexpr int BLK = KC ? 32 * 128 : 4096;       // LDS bytes between a wave's blocks
+        if (interior) {
+#pragma unroll
+            for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, voff, i * ustride);
+        } else if constexpr (KC) {
+            const bool kv = kt * BK + kofs < K;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, (kv && i < rows_valid) ? voff : OOB, i * ustride);
+        } else {
+            const int k0 = kt * BK + kofs;
+#pragma unroll
+            for (int i = 0; i < NL; ++i)
+                dma(rs, lds + lds_w + i * BLK, (mn_valid && k0 + i * 4 * KR < K) ? voff : OOB, i * ustride);
+        }
+    }
+};
+
+// Wait for this wave's LDS-DMA loads to land.
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
 // MFMA operand fragments
 //
 // 32x32 MFMAs (f16/bf16/f8): lane l feeds row (l % 32) of the A block (and
@@ -279,16 +370,53 @@ __device__ __forceinline__ int frag_chunk(int ks, int q, int s) {
     else return ks * 2 * Frag<C>::CPM + q * Frag<C>::CPM + s;
 }
 
+// One 16-bit MFMA operand fragment from a !KC operand stage (k-rows of ROWS
+// values, chunk-swizzled): lane l needs rows base + l%32 at k = 8(l/32)..+7 of
+// k-step ks.  ds_read_b64_tr_b16 hands lane l of a 16-lane group element l%4
+// of the 4-value runs read by lanes 4e + (l%16)/4, e = 0..3, so source lane
+// s (s16 = s%16, group g = s/16) reads k-row ks*16 + 8(g/2) + 4h + s16/4 at
+// rows base + 16(g%2) + 4(s16%4); two reads (h = 0, 1) give the 8 k values.
+template <class C, int ROWS>
+__device__ __forceinline__ u32x4 frag_tr(const char *op, uint32_t base, int ks, int lane) {
+    typedef short s16x4 __attribute__((ext_vector_type(4)));
+    constexpr int RB = ROWS * 2;
+    const int g = lane >> 4, s16 = lane & 15;
+    const uint32_t r0 = base + 16 * (g & 1) + 4 * (s16 & 3);
+    const uint32_t p = (uint32_t)(ks * 16 + 8 * (g >> 1) + (s16 >> 2));
+    const uint32_t off = p * RB + ((((r0 >> 3) ^ (4u * (s16 >> 2)))) << 4) + (r0 & 7) * 2;
+    const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)(op + off));
+    const s16x4 hi =
+        __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)(op + off + 4 * RB));
+    const u32x2 l2 = __builtin_bit_cast(u32x2, lo), h2 = __builtin_bit_cast(u32x2, hi);
+    return u32x4{l2[0], l2[1], h2[0], h2[1]};
+}
+
 template <class C>
 __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const char *ldsB, uint32_t arow,
                                            uint32_t brow, int ks, int q) {
+    if constexpr (C::DMA && !C::AKC) {
+        const int lane = (int)(arow % 32) + 32 * q;
 #pragma unroll
-    for (int s = 0; s < Frag<C>::CPM; ++s) {
-        const int c = frag_chunk<C>(ks, q, s);
+        for (int i = 0; i < C::FM; ++i) f.a[i][0] = frag_tr<C, C::BM>(ldsA, arow - arow % 32 + i * C::MT, ks, lane);
+    } else {
 #pragma unroll
-        for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
+        for (int s = 0; s < Frag<C>::CPM; ++s) {
+            const int c = frag_chunk<C>(ks, q, s);
 #pragma unroll
-        for (int j = 0; j < C::FN; ++j) f.b[j][s] = *(const u32x4 *)(ldsB + lds_off(brow + j * C::MT, c));
+            for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
+        }
+    }
+    if constexpr (C::DMA && !C::BKC) {
+        const int lane = (int)(brow % 32) + 32 * q;
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) f.b[j][0] = frag_tr<C, C::BN>(ldsB, brow - brow % 32 + j * C::MT, ks, lane);
+    } else {
+#pragma unroll
+        for (int s = 0; s < Frag<C>::CPM; ++s) {
+            const int c = frag_chunk<C>(ks, q, s);
+#pragma unroll
+            for (int j = 0; j < C::FN; ++j) f.b[j][s] = *(const u32x4 *)(ldsB + lds_off(brow + j * C::MT, c));
+        }
     }
 }
 
@@ -338,9 +466,39 @@ __device__ __forceinline__ void mfma_step(typename C::Frag (&acc)[C::FM][C::FN],
 // ---------------------------------------------------------------------------
 template <class C>
 struct Ctx {
-    Stage<C, C::BM, C::AKC> sa;
-    Stage<C, C::BN, C::BKC> sb;
+    typename std::conditional<C::DMA, StageDma<C, C::BM, C::AKC>, Stage<C, C::BM, C::AKC>>::type sa;
+    typename std::conditional<C::DMA, StageDma<C, C::BN, C::BKC>, Stage<C, C::BN, C::BKC>>::type sb;
 };
+
+// One k-tile of a DMA configuration: the LDS-DMA loads of k-tile i+1 go to
+// the other LDS buffer (free since the last barrier) while the k-steps of
+// k-tile i run; the wave waits for its loads, one barrier, then the first
+// fragments of k-tile i+1 are read.  P: which buffer holds k-tile i.  The
+// two buffers are distinct LDS objects, so the compiler can tell that the
+// fragment reads of one never wait for the DMA writes into the other.
+template <class C, bool FIRST, int P>
+__device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
+                                          char *lds0, char *lds1, int it, int it1, bool rows_in, int kfull, int K,
+                                          uint32_t arow, uint32_t brow, int q) {
+    constexpr int NSUB = Frag<C>::NSUB;
+    const bool more = it + 1 < it1;
+    const char *st = P ? lds1 : lds0;
+    char *nx = P ? lds0 : lds1;
+    if (more) {
+        const bool in = rows_in && it + 1 < kfull;
+        cx.sa.issue(nx, it + 1, K, in);
+        cx.sb.issue(nx + C::A_BYTES, it + 1, K, in);
+    }
+#pragma unroll
+    for (int ks = 0; ks < NSUB; ++ks) {
+        if (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
+        if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
+        else mfma_step<C, false>(acc, f[ks & 1]);
+    }
+    wait_dma();
+    __syncthreads();
+    if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
+}
 
 // One k-tile.  FIRST: the segment's first k-tile, whose first k-step starts
 // the accumulators from zero.  P: parity of the k-tile within the segment,
@@ -348,12 +506,13 @@ struct Ctx {
 // one is written to LDS).
 template <class C, bool FIRST, int P>
 __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
-                                      char *lds, int it, int it0, int it1, bool rows_in, int kfull, int K,
-                                      uint32_t arow, uint32_t brow, int q) {
+                                      char *lds0, char *lds1, int it, int it0, int it1, bool rows_in, int kfull,
+                                      int K, uint32_t arow, uint32_t brow, int q) {
     constexpr int NSUB = Frag<C>::NSUB;
     constexpr int LD = C::RSETS == 2 ? P : 0;          // set receiving the new loads
     constexpr int ST = C::RSETS == 2 ? P ^ 1 : 0;      // set written to LDS
-    const int cur = (it - it0) & 1;
+    // with two register sets the k-tiles run in pairs and P is the buffer
+    const int cur = C::RSETS == 2 ? P : (it - it0) & 1;
     const bool more = it + 1 < it1;
     const int ahead = it + C::RSETS;
     if (ahead < it1) {
@@ -361,8 +520,8 @@ __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::F
         cx.sa.template load<LD>(ahead, K, in);
         cx.sb.template load<LD>(ahead, K, in);
     }
-    const char *st = lds + cur * C::STAGE;
-    char *nx = lds + (cur ^ 1) * C::STAGE;
+    const char *st = cur ? lds1 : lds0;
+    char *nx = cur ? lds0 : lds1;
 #pragma unroll
     for (int ks = 0; ks < NSUB; ++ks) {
         if (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
@@ -379,7 +538,8 @@ __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::F
 
 template <class C>
 __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int it0, int it1,
-                                         typename C::Frag (&acc)[C::FM][C::FN], char *lds, int tid) {
+                                         typename C::Frag (&acc)[C::FM][C::FN], char *lds0, char *lds1,
+                                         int tid) {
     if (it0 >= it1) {
         // an empty range (never produced by the planner, which sends k == 0
         // work to the C = beta*C kernel): zero accumulators via a
@@ -406,7 +566,22 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
     cx.sb.init(P.B, P.ldb, col0, P.n, tid);
     const bool rows_in = (row0 + C::BM <= P.m) && (col0 + C::BN <= P.n);
     const int kfull = P.k / C::BK;                 // k-tiles with no k edge
-    {
+    if constexpr (C::DMA) {
+        const bool in = rows_in && it0 < kfull;
+        cx.sa.issue(lds0, it0, P.k, in);
+        cx.sb.issue(lds0 + C::A_BYTES, it0, P.k, in);
+        wait_dma();
+        __syncthreads();
+        Frag<C> f[2];
+        read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
+        ktile_dma<C, true, 0>(cx, f, acc, lds0, lds1, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+        // k-tiles in pairs so the LDS buffer of each is a constant
+        for (int it = it0 + 1; it < it1; it += 2) {
+            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, it, it1, rows_in, kfull, P.k, arow, brow, q);
+            if (it + 1 < it1)
+                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, it + 1, it1, rows_in, kfull, P.k, arow, brow, q);
+        }
+    } else {
         const bool in = rows_in && it0 < kfull;
         cx.sa.template load<0>(it0, P.k, in);
         cx.sb.template load<0>(it0, P.k, in);
@@ -415,23 +590,24 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
             cx.sa.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
             cx.sb.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
         }
-        cx.sa.template store<0>(lds);
-        cx.sb.template store<0>(lds + C::A_BYTES);
-    }
-    __syncthreads();
-    Frag<C> f[2];
-    read_frags<C>(f[0], lds, lds + C::A_BYTES, arow, brow, 0, q);
-    ktile<C, true, 0>(cx, f, acc, lds, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-    if constexpr (C::RSETS == 2) {
-        // k-tiles in pairs so the register-set parity is a constant
-        for (int it = it0 + 1; it < it1; it += 2) {
-            ktile<C, false, 1>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-            if (it + 1 < it1)
-                ktile<C, false, 0>(cx, f, acc, lds, it + 1, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+        cx.sa.template store<0>(lds0);
+        cx.sb.template store<0>(lds0 + C::A_BYTES);
+        __syncthreads();
+        Frag<C> f[2];
+        read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
+        ktile<C, true, 0>(cx, f, acc, lds0, lds1, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+        if constexpr (C::RSETS == 2) {
+            // k-tiles in pairs so the register-set parity is a constant
+            for (int it = it0 + 1; it < it1; it += 2) {
+                ktile<C, false, 1>(cx, f, acc, lds0, lds1, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+                if (it + 1 < it1)
+                    ktile<C, false, 0>(cx, f, acc, lds0, lds1, it + 1, it0, it1, rows_in, kfull, P.k, arow, brow,
+                                       q);
+            }
+        } else {
+            for (int it = it0 + 1; it < it1; ++it)
+                ktile<C, false, 0>(cx, f, acc, lds0, lds1, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
         }
-    } else {
-        for (int it = it0 + 1; it < it1; ++it)
-            ktile<C, false, 0>(cx, f, acc, lds, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
     }
 }
 
@@ -788,7 +964,9 @@ __device__ __forceinline__ int tile_of_iter(const Params &p, int it) {
 // keeps the code (and its register allocation) in one piece.
 template <class C, bool DP_ONLY>
 __device__ __forceinline__ void sk_body(const Params &p) {
-    __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+    // the two k-tile buffers of the MAC loop
+    __shared__ __attribute__((aligned(16))) char lds0[C::STAGE];
+    __shared__ __attribute__((aligned(16))) char lds1[C::STAGE];
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
     int x = b;
@@ -848,7 +1026,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         int tid = tid0;
         asm volatile("" : "+v"(tid));
         typename C::Frag acc[C::FM][C::FN];
-        mac_loop<C>(P, tm, tn, k0, k1, acc, lds, tid);
+        mac_loop<C>(P, tm, tn, k0, k1, acc, lds0, lds1, tid);
         if (!started) {
             store_partial<C>((char *)p.partials + (int64_t)x * C::SLOT_BYTES, acc, tid);
             signal_flag(p.flags + x * FLAG_STRIDE, tid);
