@@ -111,6 +111,9 @@ struct Cfg {
     // an operand contiguous along m (n) keeps its natural layout in LDS and
     // is transposed by the LDS transpose reads that build its fragments.
     static constexpr bool DMA = D == Dt::F16 || D == Dt::BF16;
+    // the first fixup peer is staged through LDS (not for the 256x256 FP8
+    // tile, whose register-staged MAC loop leaves no registers for it)
+    static constexpr bool FIX_LDS = RSETS == 2 || DMA;
     using Acc = typename DtTraits<D>::Acc;
     using Frag = typename DtTraits<D>::Frag;
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
@@ -699,21 +702,36 @@ struct PartialLayout {
 };
 
 // One fragment of a partial tile, as a whole vector.
+// Cache policy of every partial-tile and flag access: device scope (SC1).
+// The eight XCDs have separate L2 caches; accesses with device scope are
+// coherent across them by themselves, so publishing a partial tile needs
+// neither an L2 write-back on the producer side nor an L2 invalidate on the
+// owner side (the agent-scope release/acquire fences would issue both, and
+// an invalidate per poll evicts the operand tiles of every other workgroup on
+// that XCD).
+constexpr int CPOL_DEVICE = 16;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const char *slot, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)slot, (short)0, bytes, 0x00020000);
+}
+
 template <class C>
 __device__ __forceinline__ typename C::Frag load_partial_frag(const char *slot, int i, int j, int tid) {
     using PL = PartialLayout<C>;
+    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot, C::SLOT_BYTES);
+    u32x4 c[PL::CPF];
+#pragma unroll
+    for (int s = 0; s < PL::CPF; ++s)
+        c[s] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)PL::off(i, j, s, tid),
+                                                                             0, CPOL_DEVICE));
     if constexpr (PL::PER == 4) {
-        const f32x4 c0 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 0, tid)));
-        const f32x4 c1 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 1, tid)));
-        const f32x4 c2 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 2, tid)));
-        const f32x4 c3 = __builtin_bit_cast(f32x4, *(const u32x4 *)(slot + PL::off(i, j, 3, tid)));
-        const f32x8 lo = __builtin_shufflevector(c0, c1, 0, 1, 2, 3, 4, 5, 6, 7);
-        const f32x8 hi = __builtin_shufflevector(c2, c3, 0, 1, 2, 3, 4, 5, 6, 7);
+        const f32x8 lo = __builtin_shufflevector(__builtin_bit_cast(f32x4, c[0]), __builtin_bit_cast(f32x4, c[1]), 0,
+                                                 1, 2, 3, 4, 5, 6, 7);
+        const f32x8 hi = __builtin_shufflevector(__builtin_bit_cast(f32x4, c[2]), __builtin_bit_cast(f32x4, c[3]), 0,
+                                                 1, 2, 3, 4, 5, 6, 7);
         return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
     } else {
-        const f64x2 c0 = __builtin_bit_cast(f64x2, *(const u32x4 *)(slot + PL::off(i, j, 0, tid)));
-        const f64x2 c1 = __builtin_bit_cast(f64x2, *(const u32x4 *)(slot + PL::off(i, j, 1, tid)));
-        return __builtin_shufflevector(c0, c1, 0, 1, 2, 3);
+        return __builtin_shufflevector(__builtin_bit_cast(f64x2, c[0]), __builtin_bit_cast(f64x2, c[1]), 0, 1, 2, 3);
     }
 }
 
@@ -727,6 +745,88 @@ __device__ __forceinline__ typename C::Frag add_peers(typename C::Frag v, const 
     return v;
 }
 
+// The first peer's partial tile is staged through the (then idle) MAC-loop
+// LDS buffers by LDS-DMA loads, in FIX_PH phases, so its fragments are read
+// with LDS latency instead of one global round trip each.  Each wave stages
+// exactly the chunks its own lanes read back (partial chunk v of thread t
+// sits at v*4096 + 16t in both places), so a wave only waits for its own
+// loads; a barrier after the epilogue keeps the next unit's DMA away.
+template <class C>
+struct FixStage {
+    static constexpr int PH = C::SLOT_BYTES > 2 * C::STAGE ? 2 : 1;   // phases
+    static constexpr int VPH = C::ACC_CHUNKS / PH;                    // chunks per thread per phase
+    static constexpr int H = VPH / 2;                                 // chunks per buffer
+    static constexpr int ROWS_PH = C::FM / PH;                        // fragment rows per phase
+    static_assert(H * 4096 <= C::STAGE && C::FM % PH == 0 && VPH % 2 == 0, "fixup staging fits the LDS");
+
+    // stage chunks [ph*VPH, (ph+1)*VPH) of the slot
+    __device__ static __forceinline__ void issue(const char *slot, char *lds0, char *lds1, int ph, int tid) {
+        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot, C::SLOT_BYTES);
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+#pragma unroll
+        for (int u = 0; u < VPH; ++u) {
+            char *dst = (u < H ? lds0 : lds1) + (u % H) * 4096 + w * 1024;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16,
+                                                     (uint32_t)tid * 16u, (uint32_t)((ph * VPH + u) * 4096), 0,
+                                                     CPOL_DEVICE);
+        }
+    }
+
+    // fragment (i, j) of the staged slot
+    __device__ static __forceinline__ typename C::Frag frag(const char *lds0, const char *lds1, int i, int j,
+                                                            int tid) {
+        using PL = PartialLayout<C>;
+        u32x4 c[PL::CPF];
+#pragma unroll
+        for (int s = 0; s < PL::CPF; ++s) {
+            const int u = (i * C::FN + j) * PL::CPF + s - (i / ROWS_PH) * VPH;
+            c[s] = *(const u32x4 *)((u < H ? lds0 : lds1) + (u % H) * 4096 + tid * 16);
+        }
+        if constexpr (PL::PER == 4) {
+            const f32x8 lo = __builtin_shufflevector(__builtin_bit_cast(f32x4, c[0]), __builtin_bit_cast(f32x4, c[1]),
+                                                     0, 1, 2, 3, 4, 5, 6, 7);
+            const f32x8 hi = __builtin_shufflevector(__builtin_bit_cast(f32x4, c[2]), __builtin_bit_cast(f32x4, c[3]),
+                                                     0, 1, 2, 3, 4, 5, 6, 7);
+            return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+        } else {
+            return __builtin_shufflevector(__builtin_bit_cast(f64x2, c[0]), __builtin_bit_cast(f64x2, c[1]), 0, 1, 2,
+                                           3);
+        }
+    }
+};
+
+// acc + the peers' partial fragments (i, j), ascending slot order; the first
+// peer's fragment comes from the LDS staging.  The accumulator copy is made
+// opaque where it is used, so the copies of all fragments are not hoisted
+// to the start of the epilogue (which exhausts the VGPRs).
+template <class C>
+__device__ __forceinline__ typename C::Frag fix_frag(const typename C::Frag &a, const char *slots, int p0, int p1,
+                                                     const char *lds0, const char *lds1, int i, int j, int tid) {
+    if constexpr (!C::FIX_LDS) {
+        return add_peers<C>(a, slots, p0, p1, i, j, tid);
+    } else {
+        typename C::Frag v = a;
+        asm volatile("" : "+v"(v));
+        if (p0 <= p1) {
+            v = v + FixStage<C>::frag(lds0, lds1, i, j, tid);
+            v = add_peers<C>(v, slots, p0 + 1, p1, i, j, tid);
+        }
+        return v;
+    }
+}
+
+// Phase boundary of the staged fixup: stage the phase's chunks of the first
+// peer (after this wave's reads of the previous phase) and wait for them.
+template <class C>
+__device__ __forceinline__ void fix_phase(bool staged, const char *slots, int p0, char *lds0, char *lds1, int i,
+                                          int tid) {
+    if (C::FIX_LDS && staged && i % FixStage<C>::ROWS_PH == 0) {
+        if (i > 0) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        FixStage<C>::issue(slots + (int64_t)p0 * C::SLOT_BYTES, lds0, lds1, i / FixStage<C>::ROWS_PH, tid);
+        wait_dma();
+    }
+}
+
 // C_tile = alpha * (acc + partials of slots [p0, p1]) + beta * C_tile (C read
 // only when beta != 0), rounded once to the output type.  The accumulators
 // are only read here: each fragment is copied, completed with the peers'
@@ -736,7 +836,7 @@ __device__ __forceinline__ typename C::Frag add_peers(typename C::Frag v, const 
 template <class C, int CT>
 __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
                                              const typename C::Frag (&acc)[C::FM][C::FN], int tid,
-                                             const char *slots, int p0, int p1) {
+                                             const char *slots, int p0, int p1, char *lds0, char *lds1) {
     using Acc = typename C::Acc;
     constexpr int EB = CBytes<CT>::v;
     constexpr int G = C::FRAG_N / 4;                 // column groups per fragment
@@ -750,9 +850,11 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
         // consecutive bytes of one row
         const int r0 = tm * C::BM + wm * C::WTM + (lane >> 4);
         const int c0 = tn * C::BN + wn * C::WTN + (lane & 15);
+        const bool staged = p0 <= p1;
         static_for<C::FM * C::FN>([&](auto ij) {
             constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
-            const typename C::Frag v = add_peers<C>(acc[i][j], slots, p0, p1, i, j, tid);
+            if constexpr (j == 0) fix_phase<C>(staged, slots, p0, lds0, lds1, i, tid);
+            const typename C::Frag v = fix_frag<C>(acc[i][j], slots, p0, p1, lds0, lds1, i, j, tid);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = r0 + i * 16 + 4 * r, col = c0 + j * 16;
@@ -769,12 +871,14 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
     }
     const int rowl = tm * C::BM + wm * C::WTM + (lane % C::MT);
     const int coll = tn * C::BN + wn * C::WTN + 4 * (lane / C::MT);
+    const bool staged = p0 <= p1;
     static_for<C::FM * C::FN>([&](auto ij) {
         constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
+        if constexpr (j == 0) fix_phase<C>(staged, slots, p0, lds0, lds1, i, tid);
         const int row = rowl + i * C::MT;
         char *rp = (char *)P.C + ((int64_t)row * P.ldc + coll) * EB;
         {
-            const typename C::Frag f = add_peers<C>(acc[i][j], slots, p0, p1, i, j, tid);
+            const typename C::Frag f = fix_frag<C>(acc[i][j], slots, p0, p1, lds0, lds1, i, j, tid);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int co = j * C::MT + 8 * g;         // column offset from coll
@@ -803,21 +907,25 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
 template <class C>
 __device__ __forceinline__ void store_tile(const Problem &P, int tm, int tn,
                                            const typename C::Frag (&acc)[C::FM][C::FN], int tid,
-                                           const char *slots = nullptr, int p0 = 0, int p1 = -1) {
+                                           const char *slots, int p0, int p1, char *lds0, char *lds1) {
     if constexpr (C::DT == Dt::F64) {
-        store_tile_t<C, SK_F64>(P, tm, tn, acc, tid, slots, p0, p1);
+        store_tile_t<C, SK_F64>(P, tm, tn, acc, tid, slots, p0, p1, lds0, lds1);
     } else {
         switch (P.c_type) {
-        case SK_F32: store_tile_t<C, SK_F32>(P, tm, tn, acc, tid, slots, p0, p1); break;
-        case SK_F16: store_tile_t<C, SK_F16>(P, tm, tn, acc, tid, slots, p0, p1); break;
-        default: store_tile_t<C, SK_BF16>(P, tm, tn, acc, tid, slots, p0, p1); break;
+        case SK_F32: store_tile_t<C, SK_F32>(P, tm, tn, acc, tid, slots, p0, p1, lds0, lds1); break;
+        case SK_F16: store_tile_t<C, SK_F16>(P, tm, tn, acc, tid, slots, p0, p1, lds0, lds1); break;
+        default: store_tile_t<C, SK_BF16>(P, tm, tn, acc, tid, slots, p0, p1, lds0, lds1); break;
         }
     }
+    // the staged fixup used this wave's LDS regions: keep the next unit's
+    // loads out until every wave is done with them
+    if (C::FIX_LDS && p0 <= p1) __syncthreads();
 }
 
 template <class C>
 __device__ __forceinline__ void store_partial(char *slot, const typename C::Frag (&acc)[C::FM][C::FN], int tid) {
     using PL = PartialLayout<C>;
+    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot, C::SLOT_BYTES);
     static_for<C::FM * C::FN>([&](auto ij) {
         constexpr int i = decltype(ij)::value / C::FN, j = decltype(ij)::value % C::FN;
         {
@@ -835,7 +943,8 @@ __device__ __forceinline__ void store_partial(char *slot, const typename C::Frag
                     w[0] = (uint32_t)x0; w[1] = (uint32_t)(x0 >> 32);
                     w[2] = (uint32_t)x1; w[3] = (uint32_t)(x1 >> 32);
                 }
-                *(u32x4 *)(slot + PL::off(i, j, s, tid)) = w;
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), rs, (uint32_t)PL::off(i, j, s, tid),
+                                                       0, CPOL_DEVICE);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -843,18 +952,22 @@ __device__ __forceinline__ void store_partial(char *slot, const typename C::Frag
 }
 
 // ---------------------------------------------------------------------------
-// flags: release after the partial stores, acquire before reading them
+// flags.  Partial tiles and flags are all device-coherent accesses (SC1):
+// the producer waits until its partial stores have completed, then one
+// thread raises the flag; the owner polls the flag and issues its partial
+// loads only after it has seen it.  Program order plus completion waits
+// order the accesses; no cache-wide fence is needed.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void signal_flag(int32_t *flag, int tid) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this thread's partial stores
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's partial stores are done
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void wait_flag(int32_t *flag, int32_t *err, int limit, int tid) {
     if (tid == 0) {
         int n = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             __builtin_amdgcn_s_sleep(1);
             if (++n >= limit) {             // bounded: give up, report, never hang
                 __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -863,8 +976,9 @@ __device__ __forceinline__ void wait_flag(int32_t *flag, int32_t *err, int limit
         }
         __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // consumed
     }
+    // the workgroup barrier (with its compiler-level ordering) keeps every
+    // wave's partial loads behind the observed flag
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ __forceinline__ void trace_rec(const Params &p, int wg, int seq, int tile, int k0, int k1,
@@ -1042,7 +1156,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         }
         // peers' partial tiles are added in ascending slot order inside the
         // epilogue, fragment by fragment
-        store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last);
+        store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last, lds0, lds1);
         trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER),
                   last, tid);
     }
