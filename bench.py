@@ -5,14 +5,16 @@ Workload (one "step"): the geometry sweep -- 2048 GEMMs with m, n, k drawn
 log-uniformly from [128, 8192] (seed 1, rounded to multiples of 8), FP16
 inputs uniform in [-1, 1], FP32 accumulation and output, alpha = 1,
 beta = 0, row-major -- each run once through sk_gemm with the library's
-default schedule (two-tile Stream-K + data-parallel hybrid, one tile per
-precision).  Inputs are resident in HBM before timing starts.
+default configuration (basic Stream-K while the tiles cannot give every CU
+a workgroup, data-parallel otherwise; 128x128 tiles unless a problem has 8
+full waves of them).  Inputs are resident in HBM before timing starts.
 
 Reported on one JSON line: aggregate TFLOP/s of the step (value), % of the
 FP16 dense MFMA peak, per-GEMM latency p50/p99, the same sweep under the
-data-parallel and basic Stream-K schedules (the paper's comparison), the
-roofline of the dominant kernel measured with HIP events on the launch
-stream, and the CPU oracle timed on a bounded sample of the same workload.
+data-parallel, basic Stream-K and the paper's two-tile Stream-K + DP hybrid
+schedules (the paper's comparison), the roofline of the dominant kernel
+measured with HIP events on the launch stream, and the CPU oracle timed on a
+bounded sample of the same workload.
 
 `--extended` adds the FP64 sweep and the precision set (BF16 and FP8 on
 8192^3, 256x256x65536, 4096x1024x4096).
@@ -126,22 +128,23 @@ class Runner:
             durations.append([self.ev0[i].elapsed_time(self.ev1[i]) for i in range(len(self.dptrs))])
 
 
-def measured_traffic():
-    """HBM bytes per launch of the Stream-K kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/*_traffic.md with a machine-readable line for that kernel), or
+    None when there is none or the kernel source changed since it was taken."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sk_kernel_f16_256_sweep_traffic.md")
     src = os.path.join(ROOT, "paper_2301_03598_amd", "csrc", "sk_kernel.hpp")
-    try:
-        rec = None
-        for line in open(path):
-            if line.startswith("machine-readable: "):
-                rec = json.loads(line[len("machine-readable: "):])
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if rec and rec.get("kernel_source_sha256_16") == h:
-            return rec["traffic_bytes_per_launch"]
-    except OSError:
-        pass
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        try:
+            for line in open(path):
+                if line.startswith("machine-readable: "):
+                    rec = json.loads(line[len("machine-readable: "):])
+                    if rec.get("kernel") == kernel and rec.get("kernel_source_sha256_16") == h:
+                        return rec["traffic_bytes_per_launch"]
+        except OSError:
+            pass
     return None
 
 
@@ -156,6 +159,14 @@ def pct(xs, q):
         return 0.0
     idx = min(len(ys) - 1, max(0, int(math.ceil(q / 100.0 * len(ys))) - 1))
     return ys[idx]
+
+
+def kernel_of(pl) -> str:
+    """The kernel symbol a planned launch runs (data-parallel or Stream-K
+    entry, tile)."""
+    from paper_2301_03598_amd import streamk as S
+    kern = "dp_kernel" if pl.sched == S.SK_SCHED_DP else "sk_kernel"
+    return f"{kern}<F16, {pl.blk_m}x{pl.blk_n}x{pl.blk_k}, A k-contiguous, B n-contiguous>"
 
 
 def schedule_leg(sweep, sched, passes=2):
@@ -177,7 +188,7 @@ def schedule_leg(sweep, sched, passes=2):
     return {"tflops": round(sweep.total_flops / wall / 1e12, 2),
             "kernel_tflops": round(sweep.total_flops / (sum(per) * 1e-3) / 1e12, 2),
             "geomean_tflops": round(geomean(tf), 2),
-            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, warm + durs
+            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, (run, warm + durs)
 
 
 def cpu_baseline(budget_flops=7.0e11):
@@ -213,7 +224,7 @@ def extended():
     from paper_2301_03598_amd import streamk as S
     out = {}
     sw = Sweep(W.sweep_shapes(), "f64", "f64", seed=11)
-    for sched in ("dp", "sk", "auto"):
+    for sched in ("dp", "sk", "2tsk", "auto"):
         out[f"f64_sweep_{sched}"], _, _ = schedule_leg(sw, sched, passes=1)
         log("f64", sched, out[f"f64_sweep_{sched}"])
     del sw
@@ -389,7 +400,11 @@ def main():
     kinds = {}
     for pl in run.plans:
         kinds[S.SCHED_NAME.get(pl.sched, str(pl.sched))] = kinds.get(S.SCHED_NAME.get(pl.sched, str(pl.sched)), 0) + 1
-    log("schedules resolved:", kinds)
+    tiles = {}
+    for pl in run.plans:
+        key = f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}"
+        tiles[key] = tiles.get(key, 0) + 1
+    log("schedules resolved:", kinds, "tiles:", tiles)
 
     all_durs = []
     for w in range(args.warmup):
@@ -403,41 +418,52 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = wall / args.steps * 1e3
     value = sweep.total_flops / (ms_step * 1e-3) / 1e12
-    log(f"hybrid sweep: {ms_step:.2f} ms/step, {value:.1f} TFLOP/s")
+    log(f"default sweep: {ms_step:.2f} ms/step, {value:.1f} TFLOP/s")
     all_durs += timed
     per = [sum(d[i] for d in timed) / len(timed) for i in range(len(shapes))]
     lat_us = [x * 1e3 for x in per]
     tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
 
+    # every launch of this run is timed: durations and flops per kernel symbol
+    per_kernel = {}
+
+    def account(run_, durs_):
+        for d in durs_:
+            for i, pl in enumerate(run_.plans):
+                e = per_kernel.setdefault(kernel_of(pl), [0.0, 0.0, 0])
+                e[0] += d[i]
+                e[1] += sweep.flops[i]
+                e[2] += 1
+    account(run, all_durs)
     compare = {}
-    sk_launch_durs, sk_launch_flops = [], []
-    # every launch of the Stream-K kernel in this run is timed; the roofline
-    # averages over exactly the launches a kernel-trace profile sees
-    for d in all_durs:
-        sk_launch_durs += d
-        sk_launch_flops += sweep.flops
     if not args.no_compare:
-        dp, tf_dp, _ = schedule_leg(sweep, "dp")
-        sk, tf_sk, sk_durs = schedule_leg(sweep, "sk")
-        for d in sk_durs:               # same kernel symbol as the hybrid
-            sk_launch_durs += d
-            sk_launch_flops += sweep.flops
-        compare = {"dp": dp, "sk_basic": sk,
-                   "hybrid": {"tflops": round(value, 2), "geomean_tflops": round(geomean(tf), 2),
-                              "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2)},
-                   "geomean_speedup_hybrid_vs_dp": round(geomean([a / b for a, b in zip(tf, tf_dp)]), 3),
-                   "geomean_speedup_sk_vs_dp": round(geomean([a / b for a, b in zip(tf_sk, tf_dp)]), 3),
-                   "min_speedup_hybrid_vs_dp": round(min(a / b for a, b in zip(tf, tf_dp)), 3),
-                   "max_speedup_hybrid_vs_dp": round(max(a / b for a, b in zip(tf, tf_dp)), 3)}
+        legs = {}
+        for name, sched in (("dp", "dp"), ("sk_basic", "sk"), ("hybrid_2tile", "2tsk"), ("dp_1tile_sk", "dp1sk")):
+            res, tf_leg, (run_leg, durs_leg) = schedule_leg(sweep, sched)
+            account(run_leg, durs_leg)
+            legs[name] = (res, tf_leg)
+            del run_leg
+        compare = {k: v[0] for k, v in legs.items()}
+        compare["default"] = {"tflops": round(value, 2), "geomean_tflops": round(geomean(tf), 2),
+                              "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2)}
+        tf_dp = legs["dp"][1]
+        for name, tfl in (("default", tf), ("sk_basic", legs["sk_basic"][1]), ("hybrid_2tile", legs["hybrid_2tile"][1]),
+                          ("dp_1tile_sk", legs["dp_1tile_sk"][1])):
+            compare[f"geomean_speedup_{name}_vs_dp"] = round(geomean([a / b for a, b in zip(tfl, tf_dp)]), 3)
+        compare["min_speedup_default_vs_dp"] = round(min(a / b for a, b in zip(tf, tf_dp)), 3)
+        compare["max_speedup_default_vs_dp"] = round(max(a / b for a, b in zip(tf, tf_dp)), 3)
         log("compare:", compare)
-    avg_ms = sum(sk_launch_durs) / len(sk_launch_durs)
-    avg_flops = sum(sk_launch_flops) / len(sk_launch_flops)
+    # the dominant kernel: the symbol with the most total time in this run
+    kname, (kms, kflops, klaunch) = max(per_kernel.items(), key=lambda kv: kv[1][0])
+    avg_ms = kms / klaunch
+    avg_flops = kflops / klaunch
     achieved = avg_flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4), "traffic": measured_traffic(),
-                "kernel": "sk_kernel<F16, 256x256x64, A k-contiguous, B n-contiguous>",
-                "launches": len(sk_launch_durs), "avg_launch_us": round(avg_ms * 1e3, 3),
-                "avg_flops_per_launch": avg_flops}
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4),
+                "traffic": measured_traffic(kname),
+                "kernel": kname, "launches": klaunch, "avg_launch_us": round(avg_ms * 1e3, 3),
+                "avg_flops_per_launch": avg_flops,
+                "time_share": round(kms / sum(v[0] for v in per_kernel.values()), 3)}
 
     ext = None
     if args.extended:
@@ -459,11 +485,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "geometry sweep: 2048 GEMMs, m,n,k log-uniform in [128,8192] rounded "
                                "to multiples of 8 (seed 1); FP16 inputs U[-1,1], FP32 accumulate "
-                               "and output; alpha=1, beta=0; row-major; library default schedule "
-                               "(two-tile Stream-K + DP hybrid)",
+                               "and output; alpha=1, beta=0; row-major; library default configuration "
+                               "(basic Stream-K while tiles < CUs, else data-parallel; 128x128 tiles "
+                               "unless 8 full waves)",
                    "problems": len(shapes), "flops_per_step": sweep.total_flops,
-                   "tile": f"{run.plans[0].blk_m}x{run.plans[0].blk_n}x{run.plans[0].blk_k}",
-                   "schedules": kinds},
+                   "tiles": tiles, "schedules": kinds},
         "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2),
         "latency_us": {"p50": round(pct(lat_us, 50), 2), "p99": round(pct(lat_us, 99), 2)},
         "geomean_tflops": round(geomean(tf), 2),

@@ -48,7 +48,7 @@ typedef enum { SK_F64 = 0, SK_F32 = 1, SK_F16 = 2, SK_BF16 = 3, SK_F8_E4M3 = 4 }
 
 /* Work decompositions (paper sections 3.2, 4 and 5.2). */
 typedef enum {
-    SK_SCHED_AUTO = 0,          /* library default: two-tile SK + DP (the paper's evaluated kernel) */
+    SK_SCHED_AUTO = 0,          /* library default: basic SK while t < CUs, else DP (measured on MI355X) */
     SK_SCHED_DP = 1,            /* data-parallel: one workgroup per output tile (Algorithm 2) */
     SK_SCHED_SK = 2,            /* basic Stream-K over all tiles (Algorithm 5), g from the model */
     SK_SCHED_DP_1TILE_SK = 3,   /* full DP waves, then SK over the remaining tiles on g = p */
@@ -92,9 +92,14 @@ typedef struct {
 /*
  * Launch configuration; every field 0 (or NULL) selects the library default.
  *  sched            sk_sched_t.
- *  blk_m/n/k        tile shape; must be one built for the dtype (see
- *                   sk_plan for the default).  Built: F64 128x128x16, 64x64x16;
- *                   F16/BF16 256x256x64, 128x128x64; F8 256x256x128, 128x128x128.
+ *  blk_m/n/k        tile shape; must be one built for the dtype.  Built:
+ *                   F64 128x128x16 (default), 64x64x16; F16/BF16 256x256x64,
+ *                   128x128x64; F8 256x256x128 (default), 128x128x128.  F16/BF16
+ *                   default: 128x128x64 unless the problem has at least 8 full
+ *                   waves of those tiles (t >= 8 p), then 256x256x64.
+ *                   AUTO's "CUs" is the device's CU count, or wg_slots divided
+ *                   by the tile's workgroups per CU by LDS (160 KiB / (2 (BM +
+ *                   BN) 128 B)) when wg_slots is given.
  *  grid             g, the number of persistent workgroups (SK schedules).
  *                   Must not exceed wg_slots: a fixup owner waits for
  *                   higher-numbered workgroups, so all g must be co-resident.

@@ -120,15 +120,19 @@ def choose_grid(T: int, I: int, p: int, consts: Tuple[float, float, float, float
 
 
 def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
-              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2) -> Plan:
-    """``T_of_region(tb, te)`` returns the iteration count of tiles [tb, te)."""
+              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0) -> Plan:
+    """``T_of_region(tb, te)`` returns the iteration count of tiles [tb, te).
+    ``cus``: the CU count that the automatic schedule compares t with."""
     t = tiles
     if t == 0:
-        return Plan(0, 0, 0, False, sched, 0, [])
+        return Plan(0, 0, 0, False, SCHED_DP if sched == SCHED_AUTO else sched, 0, [])
+    if sched == SCHED_AUTO:
+        # the library's automatic choice (a measured policy, not the paper's):
+        # basic Stream-K while the tiles cannot give every CU a workgroup,
+        # data-parallel tiles otherwise
+        sched = SCHED_SK if t < cus else SCHED_DP
     if sched == SCHED_DP:
         return Plan(t, 0, 0, True, SCHED_DP, t, list(range(t)))
-    if sched == SCHED_AUTO:
-        sched = SCHED_2T
     if sched == SCHED_SK:
         T = T_of_region(0, t)
         g = grid if grid > 0 else choose_grid(T, I_max, p, consts)
@@ -146,14 +150,15 @@ def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
         g = grid if grid > 0 else choose_grid(T, I_max, p, consts)
         g = max(1, min(g, T))
         return Plan(g, 0, t, False, SCHED_SK, t, [])
+    # a hybrid's grid carries its data-parallel waves too: it stays p (or the
+    # caller's grid) even when the Stream-K region has fewer iterations, in
+    # which case some workgroups get an empty Stream-K range
     g = grid if grid > 0 else p
     if sched == SCHED_2T and w >= threshold:
         te = r + p
-        g = max(1, min(g, T_of_region(0, te)))
         return Plan(g, 0, te, False, SCHED_2T, t, list(range(te, t)))
     # DP + one-tile SK
     tb = w * p
-    g = max(1, min(g, T_of_region(tb, t)))
     return Plan(g, tb, t, True, SCHED_DP1, t, list(range(0, tb)))
 
 
@@ -220,12 +225,18 @@ class Problems:
         return self.tile_iter_begin(te - 1) + self.iters_of_tile(te - 1) - self.tile_iter_begin(tb)
 
 
+def lds_wgs_per_cu(bm: int, bn: int) -> int:
+    """Workgroups of a tile's kernel that fit one CU by LDS alone: two k-tile
+    buffers of (BM + BN) 128-byte rows in 160 KiB."""
+    return max(1, (160 * 1024) // (2 * (bm + bn) * 128))
+
+
 def plan_problems(probs: Problems, p: int, sched: int, grid: int = 0,
-                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2) -> Plan:
+                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0) -> Plan:
     # the model's per-tile iteration count is that of the deepest tile that
     # exists: a problem with no output tiles has no MAC-loop iterations
     depth = max((I for t, I in zip(probs.tp, probs.Ip) if t > 0), default=0)
-    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold)
+    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus)
 
 
 def segments(probs: Problems, plan: Plan) -> List[List[Segment]]:

@@ -18,10 +18,11 @@ struct TileDef {
     int bm, bn, bk;
 };
 
-// Built tiles per input dtype; the first entry is the default.  The paper
+// Built tiles per input dtype; the first entry is the large tile.  The paper
 // keeps one tile per precision, the smallest that reaches its near-peak rate
-// on very large problems (section 5.1); the second entry serves the
-// autotuner and the data-parallel ensemble comparison.
+// on very large problems (section 5.1).  For FP16/BF16 the automatic choice
+// takes the second (128x128) tile unless the problem fills at least
+// kBigTileWaves full waves of it (see pick_tile).
 const TileDef kF64Tiles[] = {{128, 128, 16}, {64, 64, 16}};
 const TileDef k16Tiles[] = {{256, 256, 64}, {128, 128, 64}};
 const TileDef kF8Tiles[] = {{256, 256, 128}, {128, 128, 128}};
@@ -107,12 +108,25 @@ sk_status_t validate(const sk_gemm_desc_t &d) {
     return SK_OK;
 }
 
+// Workgroups of a tile's kernel that fit one CU by LDS alone (two k-tile
+// buffers of (BM + BN) 128-byte rows; 160 KiB per CU).
+int lds_wgs_per_cu(const TileDef &t) {
+    const int lds = 2 * (t.bm + t.bn) * 128;
+    return std::max(1, (160 * 1024) / lds);
+}
+
+// FP16/BF16 problems with at least this many full waves of 128x128 tiles
+// use the 256x256 tile (its larger per-tile reuse wins once the machine is
+// saturated many times over; below that the 128x128 tile's two workgroups
+// per CU hide more latency).
+constexpr int64_t kBigTileWaves = 8;
+
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
     int n = 0;
     const TileDef *t = tiles_for(ab, &n);
     if (!t) return SK_ERR_UNSUPPORTED;
     if (!cfg || (cfg->blk_m == 0 && cfg->blk_n == 0 && cfg->blk_k == 0)) {
-        *out = t[0];
+        *out = t[0];   // refined by pick_tile for FP16/BF16
         return SK_OK;
     }
     for (int i = 0; i < n; ++i)
@@ -134,6 +148,26 @@ struct SlotKey {
 std::mutex g_slot_mu;
 std::vector<std::pair<SlotKey, int>> g_slot_cache;
 
+std::vector<std::pair<int, int>> g_cu_cache;   // device -> CU count
+
+sk_status_t query_cus(int *cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        for (auto &e : g_cu_cache)
+            if (e.first == dev) {
+                *cus = e.second;
+                return SK_OK;
+            }
+    }
+    if (hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || *cus <= 0)
+        return SK_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_cu_cache.push_back({dev, *cus});
+    return SK_OK;
+}
+
 sk_status_t query_slots(const KernelKey &key, int *slots) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
@@ -147,8 +181,7 @@ sk_status_t query_slots(const KernelKey &key, int *slots) {
             }
     }
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        return SK_ERR_HIP;
+    if (query_cus(&cus) != SK_OK) return SK_ERR_HIP;
     KernelKey k2 = key;
     k2.dp_only = false;
     KernelEntry e = find_kernel(k2);
@@ -209,6 +242,8 @@ struct Call {
 sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, bool grouped,
                        Call *c) {
     if (!d || count <= 0) return SK_ERR_INVALID_VALUE;
+    if (cfg && (cfg->wg_slots < 0 || cfg->grid < 0 || cfg->sched < SK_SCHED_AUTO || cfg->sched > SK_SCHED_2TILE_SK_DP))
+        return SK_ERR_INVALID_VALUE;
     for (int i = 0; i < count; ++i) {
         sk_status_t s = validate(d[i]);
         if (s != SK_OK) return s;
@@ -221,6 +256,24 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
     }
     sk_status_t s = resolve_tile(d[0].ab_type, cfg, &c->tile);
     if (s != SK_OK) return s;
+    const bool tile_given = cfg && (cfg->blk_m != 0 || cfg->blk_n != 0 || cfg->blk_k != 0);
+    if (!tile_given && (d[0].ab_type == SK_F16 || d[0].ab_type == SK_BF16)) {
+        // the 128x128 tile unless there are kBigTileWaves full waves of it
+        int n = 0;
+        const TileDef small = tiles_for(d[0].ab_type, &n)[1];
+        int64_t t_small = 0;
+        for (int i = 0; i < count; ++i) {
+            const Problem p = to_problem(d[i], small.bm, small.bn, small.bk);
+            if (p.m > 0 && p.n > 0) t_small += cdiv(p.m, small.bm) * (int64_t)p.tiles_n;
+        }
+        int p_small = cfg ? cfg->wg_slots : 0;
+        if (p_small <= 0) {
+            const KernelKey ks{d[0].ab_type, small.bm, small.bn, a_kcontig(d[0]), b_kcontig(d[0]), grouped, false};
+            s = query_slots(ks, &p_small);
+            if (s != SK_OK) return s;
+        }
+        if (t_small < kBigTileWaves * (int64_t)p_small) c->tile = small;
+    }
     c->key = KernelKey{d[0].ab_type, c->tile.bm, c->tile.bn, a_kcontig(d[0]), b_kcontig(d[0]), grouped, false};
     c->probs.resize(count);
     c->tile_prefix.assign(count + 1, 0);
@@ -264,8 +317,32 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     const int64_t t = c.tiles;
     pl->xcd_remap = (cfg && (cfg->flags & SK_FLAG_NO_XCD_REMAP)) ? 0 : 1;
     if (t == 0) {
-        pl->sched = sched == SK_SCHED_AUTO ? SK_SCHED_2TILE_SK_DP : sched;
+        pl->sched = sched == SK_SCHED_AUTO ? SK_SCHED_DP : sched;
         return SK_OK;
+    }
+    int p = 0;
+    int cus = 0;
+    if (sched != SK_SCHED_DP) {
+        p = cfg ? cfg->wg_slots : 0;
+        if (p < 0) return SK_ERR_INVALID_VALUE;
+        if (p == 0) {
+            sk_status_t s = query_slots(c.key, &p);
+            if (s == SK_OK) s = query_cus(&cus);
+            if (s != SK_OK) return s;
+        } else {
+            cus = p / lds_wgs_per_cu(c.tile);
+        }
+        pl->wg_slots = p;
+        if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
+    }
+    if (sched == SK_SCHED_AUTO) {
+        // Measured on MI355X: Stream-K pays off while the tiles cannot give
+        // every CU a workgroup (t < CUs); from there on, one data-parallel
+        // workgroup per tile is at least as fast as the hybrids -- with two
+        // or more workgroups resident per CU the last partial wave costs
+        // little, while a Stream-K region loses the k-aligned L2 reuse of
+        // concurrently running tiles and pays for its fixups.
+        sched = t < cus ? SK_SCHED_SK : SK_SCHED_DP;
     }
     if (sched == SK_SCHED_DP) {
         pl->sched = SK_SCHED_DP;
@@ -274,15 +351,6 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         pl->dp_tiles = t;
         return SK_OK;
     }
-    int p = cfg ? cfg->wg_slots : 0;
-    if (p < 0) return SK_ERR_INVALID_VALUE;
-    if (p == 0) {
-        sk_status_t s = query_slots(c.key, &p);
-        if (s != SK_OK) return s;
-    }
-    pl->wg_slots = p;
-    if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
-    if (sched == SK_SCHED_AUTO) sched = SK_SCHED_2TILE_SK_DP;
     const int64_t w = t / p, r = t % p;
     int64_t skb = 0, ske = 0;
     int64_t g = 0;
@@ -307,7 +375,10 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         g = user_grid > 0 ? user_grid : p;
     }
     const int64_t sk_iters = c.region_iters(skb, ske);
-    if (sk_iters > 0) g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
+    // basic Stream-K never launches more workgroups than iterations; a
+    // hybrid's grid also carries its data-parallel waves and keeps p (some
+    // workgroups then have an empty Stream-K range)
+    if (sched == SK_SCHED_SK && sk_iters > 0) g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
     pl->sched = sched;
     pl->grid = (int32_t)g;
     pl->dp_first = sched == SK_SCHED_DP_1TILE_SK ? 1 : 0;

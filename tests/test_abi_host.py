@@ -117,7 +117,8 @@ def test_grouped_rejects_mixed_types():
 def oracle_plan(shapes, blk, p, sched, grid, threshold=2):
     geos = [O.geometry(m, n, k, *blk) for (m, n, k) in shapes]
     probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, shapes)])
-    return probs, O.plan_problems(probs, p=p, sched=sched, grid=grid, consts=MODEL, threshold=threshold)
+    cus = p // O.lds_wgs_per_cu(blk[0], blk[1])
+    return probs, O.plan_problems(probs, p=p, sched=sched, grid=grid, consts=MODEL, threshold=threshold, cus=cus)
 
 
 def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="row"):
@@ -180,3 +181,23 @@ def test_grouped_plan_matches_schedule_oracle(shapes, p, sched, grid):
     if sum(1 for (m, n, k) in shapes if m > 0 and n > 0) == 0:
         return
     check_plan_agrees(shapes, "bf16", (128, 128, 64), p, S.SCHED[sched], min(grid, p))
+
+
+def test_auto_tile_and_schedule_policy():
+    # FP16/BF16 without a tile: 128x128 unless 8 full waves of it (t >= 8 p)
+    cfg = S.make_config(wg_slots=512)
+    for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 128), (4096, 4096, 128), (256, 256, 128)):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="bf16", c_type="f32"), cfg)
+        assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, pl.blk_m)
+    # other dtypes keep their default tile
+    st, pl = S.sk_plan(desc(m=256, n=256, k=512, ab_type="f64", c_type="f64"), cfg)
+    assert st == S.SK_OK and pl.blk_m == 128
+    # AUTO: basic Stream-K while t < CUs (= wg_slots / LDS-bound workgroups per CU), else DP
+    blk = (128, 128, 64)
+    cus = 512 // O.lds_wgs_per_cu(128, 128)
+    assert cus == 256
+    for (m, n, want) in ((1024, 1024, S.SK_SCHED_SK), (2048, 2048 - 128, S.SK_SCHED_SK),
+                         (2048, 2048, S.SK_SCHED_DP), (4096, 4096, S.SK_SCHED_DP)):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="f16", c_type="f32"),
+                           S.make_config(blk=blk, wg_slots=512))
+        assert st == S.SK_OK and pl.sched == want, (m, n, pl.sched)

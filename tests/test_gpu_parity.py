@@ -152,6 +152,16 @@ def test_hybrids_on_few_slots(sched, slots, ws):
     check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
 
 
+@pytest.mark.parametrize("m,n,k", [(384, 384, 64), (256, 640, 128)])
+def test_dp1sk_region_smaller_than_grid(m, n, k, ws):
+    # DP + one-tile SK where the Stream-K region has fewer iterations than the
+    # grid (9 tiles / 1 iteration, 10 tiles / 2 iterations on 8 slots): the
+    # grid stays 8 for the DP wave and some workgroups get no SK work
+    cfg = S.make_config(sched="dp1sk", blk=(128, 128, 64), wg_slots=8)
+    _, plan = check_case(m, n, k, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
+    assert plan.grid == 8 and plan.sk_iters < plan.grid
+
+
 def test_xcd_remap_off_same_bits(ws):
     m, n, k = 512, 512, 2048
     A, B = operands(m, n, k, "bf16", 3, "normal")
