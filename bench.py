@@ -87,8 +87,14 @@ class Sweep:
 
 
 class Runner:
-    """Launches sk_gemm for every problem of a sweep on the current stream,
-    with a timing event pair around every launch."""
+    """Launches sk_gemm for every problem of a sweep on the current stream.
+
+    `step_timed` is the timed form: the launches grouped by kernel symbol
+    (the problems of one symbol back to back -- the order of a sweep's
+    independent GEMMs is free), one HIP event at each group boundary and no
+    other GPU work.  `step_events` brackets every launch with an event pair
+    (per-GEMM latency); each pair costs several microseconds of GPU time, so
+    it is kept out of the timed region."""
 
     def __init__(self, sweep, cfg):
         import torch
@@ -114,18 +120,49 @@ class Runner:
         n = len(sweep.shapes)
         self.ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
         self.ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        # problems grouped by kernel symbol, in sweep order within a group
+        self.groups = {}
+        for i, pl in enumerate(self.plans):
+            self.groups.setdefault(kernel_of(pl, sweep.ab), []).append(i)
+        self.gev = []                   # per timed step: {symbol: (start, end)}
+        self.group_ms = {k: 0.0 for k in self.groups}
+        self.group_steps = 0
 
-    def step(self, durations=None):
-        L, ws, nb = self.L, self.wsp, self.ws.nbytes
-        for i, d in enumerate(self.dptrs):
+    def _launch(self, i):
+        st = self.L.sk_gemm(self.dptrs[i], self.cfgp, self.wsp, self.ws.nbytes, self.sptr)
+        if st != 0:
+            raise RuntimeError(f"sk_gemm failed on problem {i}: {self.S.sk_status_string(st)}")
+
+    def step_plain(self):
+        for i in range(len(self.dptrs)):
+            self._launch(i)
+
+    def step_timed(self):
+        import torch
+        ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in self.groups}
+        self.gev.append(ev)
+        for k, idx in self.groups.items():
+            e0, e1 = ev[k]
+            e0.record(self.stream)
+            for i in idx:
+                self._launch(i)
+            e1.record(self.stream)
+
+    def collect_timed(self):
+        """Per-symbol GPU time of every timed step so far (after a sync)."""
+        for ev in self.gev:
+            for k, (e0, e1) in ev.items():
+                self.group_ms[k] += e0.elapsed_time(e1)
+            self.group_steps += 1
+        self.gev = []
+
+    def step_events(self, durations):
+        for i in range(len(self.dptrs)):
             self.ev0[i].record(self.stream)
-            st = L.sk_gemm(d, self.cfgp, ws, nb, self.sptr)
+            self._launch(i)
             self.ev1[i].record(self.stream)
-            if st != 0:
-                raise RuntimeError(f"sk_gemm failed on problem {i}: {self.S.sk_status_string(st)}")
-        if durations is not None:
-            self.stream.synchronize()
-            durations.append([self.ev0[i].elapsed_time(self.ev1[i]) for i in range(len(self.dptrs))])
+        self.stream.synchronize()
+        durations.append([self.ev0[i].elapsed_time(self.ev1[i]) for i in range(len(self.dptrs))])
 
 
 def measured_traffic(kernel: str):
@@ -161,34 +198,34 @@ def pct(xs, q):
     return ys[idx]
 
 
-def kernel_of(pl) -> str:
+def kernel_of(pl, ab: str = "f16") -> str:
     """The kernel symbol a planned launch runs (data-parallel or Stream-K
-    entry, tile)."""
+    entry, input type, tile; the sweeps are row-major)."""
     from paper_2301_03598_amd import streamk as S
     kern = "dp_kernel" if pl.sched == S.SK_SCHED_DP else "sk_kernel"
-    return f"{kern}<F16, {pl.blk_m}x{pl.blk_n}x{pl.blk_k}, A k-contiguous, B n-contiguous>"
+    return f"{kern}<{ab.upper()}, {pl.blk_m}x{pl.blk_n}x{pl.blk_k}, A k-contiguous, B n-contiguous>"
 
 
 def schedule_leg(sweep, sched, passes=2):
-    """Aggregate and geomean TFLOP/s of a sweep under one schedule."""
+    """Aggregate TFLOP/s of a sweep under one schedule (plain launches,
+    wall clock) and per-problem TFLOP/s from a separate event pass."""
     import torch
     from paper_2301_03598_amd import streamk as S
     run = Runner(sweep, S.make_config(sched=sched))
-    warm = []
-    run.step(warm)                  # warm-up pass
-    durs = []
+    run.step_plain()                # warm-up pass
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(passes):
-        run.step(durs)
+        run.step_plain()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / passes
-    per = [sum(d[i] for d in durs) / len(durs) for i in range(len(sweep.shapes))]
+    durs = []
+    run.step_events(durs)
+    per = durs[0]
     tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
     return {"tflops": round(sweep.total_flops / wall / 1e12, 2),
-            "kernel_tflops": round(sweep.total_flops / (sum(per) * 1e-3) / 1e12, 2),
             "geomean_tflops": round(geomean(tf), 2),
-            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, (run, warm + durs)
+            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, run
 
 
 def cpu_baseline(budget_flops=7.0e11):
@@ -284,11 +321,11 @@ def grouped_leg(tune: bool = True):
     out = {"problems": len(shapes), "flops": flops}
     # separate launches, library default per problem
     run = Runner(sw, S.make_config(sched="auto"))
-    run.step()
+    run.step_plain()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(3):
-        run.step()
+        run.step_plain()
     torch.cuda.synchronize()
     sep_ms = (time.perf_counter() - t0) / 3 * 1e3
     out["separate_launches"] = {"ms": round(sep_ms, 3), "tflops": round(flops / sep_ms / 1e9, 1)}
@@ -406,41 +443,29 @@ def main():
         tiles[key] = tiles.get(key, 0) + 1
     log("schedules resolved:", kinds, "tiles:", tiles)
 
-    all_durs = []
-    for w in range(args.warmup):
-        run.step(all_durs)
+    for _ in range(args.warmup):
+        run.step_plain()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    timed = []
     for _ in range(args.steps):
-        run.step(timed)
+        run.step_timed()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    run.collect_timed()             # per-symbol GPU time of the timed steps
     ms_step = wall / args.steps * 1e3
     value = sweep.total_flops / (ms_step * 1e-3) / 1e12
     log(f"default sweep: {ms_step:.2f} ms/step, {value:.1f} TFLOP/s")
-    all_durs += timed
-    per = [sum(d[i] for d in timed) / len(timed) for i in range(len(shapes))]
+    lat = []
+    run.step_events(lat)
+    per = lat[0]
     lat_us = [x * 1e3 for x in per]
     tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
 
-    # every launch of this run is timed: durations and flops per kernel symbol
-    per_kernel = {}
-
-    def account(run_, durs_):
-        for d in durs_:
-            for i, pl in enumerate(run_.plans):
-                e = per_kernel.setdefault(kernel_of(pl), [0.0, 0.0, 0])
-                e[0] += d[i]
-                e[1] += sweep.flops[i]
-                e[2] += 1
-    account(run, all_durs)
     compare = {}
     if not args.no_compare:
         legs = {}
         for name, sched in (("dp", "dp"), ("sk_basic", "sk"), ("hybrid_2tile", "2tsk"), ("dp_1tile_sk", "dp1sk")):
-            res, tf_leg, (run_leg, durs_leg) = schedule_leg(sweep, sched)
-            account(run_leg, durs_leg)
+            res, tf_leg, run_leg = schedule_leg(sweep, sched)
             legs[name] = (res, tf_leg)
             del run_leg
         compare = {k: v[0] for k, v in legs.items()}
@@ -453,17 +478,22 @@ def main():
         compare["min_speedup_default_vs_dp"] = round(min(a / b for a, b in zip(tf, tf_dp)), 3)
         compare["max_speedup_default_vs_dp"] = round(max(a / b for a, b in zip(tf, tf_dp)), 3)
         log("compare:", compare)
-    # the dominant kernel: the symbol with the most total time in this run
-    kname, (kms, kflops, klaunch) = max(per_kernel.items(), key=lambda kv: kv[1][0])
-    avg_ms = kms / klaunch
-    avg_flops = kflops / klaunch
+    # the dominant kernel: the symbol with the most GPU time in the timed
+    # steps; its launches ran back to back between two events in each step
+    kname = max(run.group_ms, key=lambda k: run.group_ms[k])
+    idx = run.groups[kname]
+    klaunch = len(idx) * run.group_steps
+    avg_ms = run.group_ms[kname] / klaunch
+    avg_flops = sum(sweep.flops[i] for i in idx) / len(idx)
     achieved = avg_flops / (avg_ms * 1e-3) / 1e12
+    total_ms = sum(run.group_ms.values())
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4),
                 "traffic": measured_traffic(kname),
                 "kernel": kname, "launches": klaunch, "avg_launch_us": round(avg_ms * 1e3, 3),
-                "avg_flops_per_launch": avg_flops,
-                "time_share": round(kms / sum(v[0] for v in per_kernel.values()), 3)}
+                "avg_flops_per_launch": avg_flops, "time_share": round(run.group_ms[kname] / total_ms, 3),
+                "per_kernel_avg_us": {k: round(run.group_ms[k] * 1e3 / (len(run.groups[k]) * run.group_steps), 3)
+                                      for k in run.groups}}
 
     ext = None
     if args.extended:
