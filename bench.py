@@ -496,6 +496,7 @@ def main():
                                       for k in run.groups}}
 
     ext = None
+    total_flops = sweep.total_flops
     if args.extended:
         del sweep, run
         torch.cuda.empty_cache()
@@ -518,7 +519,7 @@ def main():
                                "and output; alpha=1, beta=0; row-major; library default configuration "
                                "(basic Stream-K while tiles < CUs, else data-parallel; 128x128 tiles "
                                "unless 8 full waves)",
-                   "problems": len(shapes), "flops_per_step": sweep.total_flops,
+                   "problems": len(shapes), "flops_per_step": total_flops,
                    "tiles": tiles, "schedules": kinds},
         "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2),
         "latency_us": {"p50": round(pct(lat_us, 50), 2), "p99": round(pct(lat_us, 99), 2)},

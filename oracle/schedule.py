@@ -120,17 +120,22 @@ def choose_grid(T: int, I: int, p: int, consts: Tuple[float, float, float, float
 
 
 def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
-              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0) -> Plan:
+              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0,
+              auto_two_tile: bool = False) -> Plan:
     """``T_of_region(tb, te)`` returns the iteration count of tiles [tb, te).
-    ``cus``: the CU count that the automatic schedule compares t with."""
+    ``cus``: the CU count that the automatic schedule compares t with;
+    ``auto_two_tile``: the automatic schedule is the two-tile hybrid (FP64)."""
     t = tiles
     if t == 0:
         return Plan(0, 0, 0, False, SCHED_DP if sched == SCHED_AUTO else sched, 0, [])
     if sched == SCHED_AUTO:
         # the library's automatic choice (a measured policy, not the paper's):
         # basic Stream-K while the tiles cannot give every CU a workgroup,
-        # data-parallel tiles otherwise
-        sched = SCHED_SK if t < cus else SCHED_DP
+        # data-parallel tiles otherwise; FP64 takes the two-tile hybrid
+        if auto_two_tile:
+            sched = SCHED_2T
+        else:
+            sched = SCHED_SK if t < cus else SCHED_DP
     if sched == SCHED_DP:
         return Plan(t, 0, 0, True, SCHED_DP, t, list(range(t)))
     if sched == SCHED_SK:
@@ -232,11 +237,12 @@ def lds_wgs_per_cu(bm: int, bn: int) -> int:
 
 
 def plan_problems(probs: Problems, p: int, sched: int, grid: int = 0,
-                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0) -> Plan:
+                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0,
+                  auto_two_tile: bool = False) -> Plan:
     # the model's per-tile iteration count is that of the deepest tile that
     # exists: a problem with no output tiles has no MAC-loop iterations
     depth = max((I for t, I in zip(probs.tp, probs.Ip) if t > 0), default=0)
-    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus)
+    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus, auto_two_tile)
 
 
 def segments(probs: Problems, plan: Plan) -> List[List[Segment]]:

@@ -342,7 +342,12 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         // or more workgroups resident per CU the last partial wave costs
         // little, while a Stream-K region loses the k-aligned L2 reuse of
         // concurrently running tiles and pays for its fixups.
-        sched = t < cus ? SK_SCHED_SK : SK_SCHED_DP;
+        // FP64: a k-tile's MFMA work is long next to its operand traffic,
+        // so lost L2 reuse costs little and Stream-K's balance wins at every
+        // size (FP64 sweep: basic SK 47.5, two-tile hybrid 47.8, the rule
+        // above 43.7, DP 30.6 TFLOP/s): the paper's two-tile hybrid.
+        if (c.key.ab_type == SK_F64) sched = SK_SCHED_2TILE_SK_DP;
+        else sched = t < cus ? SK_SCHED_SK : SK_SCHED_DP;
     }
     if (sched == SK_SCHED_DP) {
         pl->sched = SK_SCHED_DP;

@@ -114,11 +114,12 @@ def test_grouped_rejects_mixed_types():
     assert S.sk_gemm_grouped(arr, None, FAKE, 1 << 20, 0) == S.SK_ERR_UNSUPPORTED
 
 
-def oracle_plan(shapes, blk, p, sched, grid, threshold=2):
+def oracle_plan(shapes, blk, p, sched, grid, threshold=2, dtype="bf16"):
     geos = [O.geometry(m, n, k, *blk) for (m, n, k) in shapes]
     probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, shapes)])
     cus = p // O.lds_wgs_per_cu(blk[0], blk[1])
-    return probs, O.plan_problems(probs, p=p, sched=sched, grid=grid, consts=MODEL, threshold=threshold, cus=cus)
+    return probs, O.plan_problems(probs, p=p, sched=sched, grid=grid, consts=MODEL, threshold=threshold, cus=cus,
+                                  auto_two_tile=dtype == "f64")
 
 
 def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="row"):
@@ -132,7 +133,7 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
     assert st == S.SK_OK, S.sk_status_string(st)
     # a column-major C is computed as C^T = B^T A^T: the tile grid is n x m
     oshapes = [(n, m, k) if c_order == "col" else (m, n, k) for (m, n, k) in shapes]
-    probs, op = oracle_plan(oshapes, blk, p, sched, grid, threshold or 2)
+    probs, op = oracle_plan(oshapes, blk, p, sched, grid, threshold or 2, dtype)
     assert pl.tiles == probs.tiles
     assert pl.iters_total == probs.total
     assert pl.grid == op.g
