@@ -95,7 +95,7 @@ typedef struct {
  *  sched            sk_sched_t.
  *  blk_m/n/k        tile shape; must be one built for the dtype.  Built:
  *                   F64 128x128x16 (default), 64x64x16; F16/BF16 256x256x64,
- *                   128x128x64; F8 256x256x128 (default), 128x128x128.  F16/BF16
+ *                   128x128x64; F8 128x128x128 (default), 256x256x128.  F16/BF16
  *                   default: 128x128x64 unless the problem has at least 8 full
  *                   waves of those tiles (t >= 8 p), then 256x256x64.
  *                   AUTO's "CUs" is the device's CU count, or wg_slots divided

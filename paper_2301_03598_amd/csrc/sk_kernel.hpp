@@ -107,13 +107,14 @@ struct Cfg {
     // load has about two k-tiles of MFMA work to arrive.  The 256x256 FP8
     // tile has no registers to spare for the second set.
     static constexpr int RSETS = (D == Dt::F8 && BM >= 256) ? 1 : 2;
-    // FP16/BF16 operands go global -> LDS directly (LDS-DMA buffer loads);
-    // an operand contiguous along m (n) keeps its natural layout in LDS and
-    // is transposed by the LDS transpose reads that build its fragments.
-    static constexpr bool DMA = D == Dt::F16 || D == Dt::BF16;
+    // FP16/BF16/FP8 operands go global -> LDS directly (LDS-DMA buffer
+    // loads); an operand contiguous along m (n) keeps its natural layout in
+    // LDS and is transposed by the LDS transpose reads that build its
+    // fragments (16-bit or 8-bit forms).
+    static constexpr bool DMA = D == Dt::F16 || D == Dt::BF16 || D == Dt::F8;
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
     // tile, whose register-staged MAC loop leaves no registers for it)
-    static constexpr bool FIX_LDS = RSETS == 2 || DMA;
+    static constexpr bool FIX_LDS = (RSETS == 2 || DMA) && !(D == Dt::F8 && BM >= 256);
     using Acc = typename DtTraits<D>::Acc;
     using Frag = typename DtTraits<D>::Frag;
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
@@ -271,18 +272,30 @@ struct Stage {
 //  KC (rows x k, k contiguous): the block is 8 rows of 128 bytes in the
 //    lds_off layout; lane L fetches row L/8, chunk (L%8) ^ ((row/2) % 8).
 //  !KC (k x rows, rows contiguous): LDS k-row p holds the tile's ROWS
-//    values (2*ROWS bytes) with 16-byte chunk c at slot c ^ 4(p % 4); the
-//    block is 1024 / (2*ROWS) k-rows.
+//    values (E*ROWS bytes) with 16-byte chunk c at slot c ^ sw(p) (see
+//    nkc_swizzle); the block is 1024 / (E*ROWS) k-rows.
 // Loads outside the matrix get an offset past the resource range and
 // deposit zeros.
 // ---------------------------------------------------------------------------
+// Chunk swizzle of k-row p in the !KC (natural) layout, chosen so that the
+// transpose reads of one fragment -- 16-bit: 4 consecutive k-rows x 32
+// bytes per 16 lanes; 8-bit: 8 consecutive k-rows x 16 bytes -- hit every
+// bank once per 256 bytes.  A k-row of 256 bytes fills the 64 banks; one of
+// 128 bytes shares them with its neighbour.
+template <int E, int ROWS>
+__device__ __forceinline__ int nkc_swizzle(int p) {
+    if constexpr (E == 2) return 4 * (p & 3);
+    else if constexpr (ROWS * E >= 256) return 2 * (p & 7);
+    else return 2 * ((p >> 1) & 3);
+}
+
 template <class C, int ROWS, bool KC>
 struct StageDma {
     static constexpr int NL = ROWS / 32;            // loads per wave per k-tile
     static constexpr int E = C::E, VEC = C::VEC, BK = C::BK;
-    static constexpr int CPR = ROWS / 8;            // !KC: chunks per k-row
+    static constexpr int CPR = ROWS * E / 16;       // !KC: chunks per k-row
     static constexpr int KR = 1024 / (ROWS * E);    // !KC: k-rows per 1 KiB block
-    static_assert(E == 2 && BK == 64, "16-bit operands, 128-byte k rows");
+    static_assert((E == 2 || E == 1) && BK * E == 128, "16- or 8-bit operands, 128-byte k rows");
     static constexpr uint32_t OOB = 0x80000000u;
     const char *ub;
     int64_t ustep;
@@ -309,7 +322,7 @@ struct StageDma {
             lds_w = (uint32_t)(8 * w * 128);
         } else {
             const int pr = w * KR + L / CPR;            // k-row of load 0 within the k-tile
-            const int c = (L % CPR) ^ (4 * (pr & 3));
+            const int c = (L % CPR) ^ nkc_swizzle<E, ROWS>(pr);
             ub = p + (int64_t)row0 * E;
             ustep = (int64_t)BK * ld * E;
             ustride = (uint32_t)(4 * KR * ld * E);
@@ -394,10 +407,40 @@ __device__ __forceinline__ u32x4 frag_tr(const char *op, uint32_t base, int ks, 
     return u32x4{l2[0], l2[1], h2[0], h2[1]};
 }
 
+// One FP8 MFMA operand fragment (32 k values per lane) from a !KC operand
+// stage: lane l needs rows base + l%32 at k = ks*64 + 32(l/32) + 0..31.
+// ds_read_b64_tr_b8 hands lane l of a 16-lane group byte l%8 of the 8-byte
+// runs read by lanes 2e + (l%16)/8, e = 0..7, so source lane s (group g)
+// reads k-row ks*64 + 32(g/2) + 8h + s/2 at rows base + 16(g%2) + 8(s%2);
+// four reads (h = 0..3) give the lane's 32 k values.
+template <class C, int ROWS>
+__device__ __forceinline__ void frag_tr8(u32x4 (&out)[2], const char *op, uint32_t base, int ks, int lane) {
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    constexpr int RB = ROWS;
+    const int g = lane >> 4, s16 = lane & 15;
+    const uint32_t r0 = base + 16 * (g & 1) + 8 * (s16 & 1);
+    uint32_t w[8];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int p = ks * 64 + 32 * (g >> 1) + 8 * h + (s16 >> 1);
+        const uint32_t off = (uint32_t)p * RB + (((r0 >> 4) ^ (uint32_t)nkc_swizzle<1, ROWS>(p)) << 4) + (r0 & 15);
+        const i32x2 v =
+            __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) i32x2 *)(op + off));
+        w[2 * h] = (uint32_t)v[0];
+        w[2 * h + 1] = (uint32_t)v[1];
+    }
+    out[0] = u32x4{w[0], w[1], w[2], w[3]};
+    out[1] = u32x4{w[4], w[5], w[6], w[7]};
+}
+
 template <class C>
 __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const char *ldsB, uint32_t arow,
                                            uint32_t brow, int ks, int q) {
-    if constexpr (C::DMA && !C::AKC) {
+    if constexpr (C::DMA && !C::AKC && C::DT == Dt::F8) {
+        const int lane = (int)(arow % 32) + 32 * q;
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) frag_tr8<C, C::BM>(f.a[i], ldsA, arow - arow % 32 + i * C::MT, ks, lane);
+    } else if constexpr (C::DMA && !C::AKC) {
         const int lane = (int)(arow % 32) + 32 * q;
 #pragma unroll
         for (int i = 0; i < C::FM; ++i) f.a[i][0] = frag_tr<C, C::BM>(ldsA, arow - arow % 32 + i * C::MT, ks, lane);
@@ -409,7 +452,11 @@ __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const c
             for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
         }
     }
-    if constexpr (C::DMA && !C::BKC) {
+    if constexpr (C::DMA && !C::BKC && C::DT == Dt::F8) {
+        const int lane = (int)(brow % 32) + 32 * q;
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) frag_tr8<C, C::BN>(f.b[j], ldsB, brow - brow % 32 + j * C::MT, ks, lane);
+    } else if constexpr (C::DMA && !C::BKC) {
         const int lane = (int)(brow % 32) + 32 * q;
 #pragma unroll
         for (int j = 0; j < C::FN; ++j) f.b[j][0] = frag_tr<C, C::BN>(ldsB, brow - brow % 32 + j * C::MT, ks, lane);
