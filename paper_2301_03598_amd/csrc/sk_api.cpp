@@ -53,9 +53,9 @@ struct Model {
 
 Model default_model(int ab, int bm) {
     switch (ab) {
-    case SK_F64: return bm >= 128 ? Model{10.8, 6.3, 2.27, 6.2} : Model{5.1, 2.4, 0.92, 2.1};
-    case SK_F8_E4M3: return bm >= 256 ? Model{20.0, 7.0, 5.5, 7.1} : Model{0.0, 13.4, 1.5, 2.5};
-    default: return bm >= 256 ? Model{20.4, 7.0, 2.0, 7.1} : Model{0.0, 14.7, 1.1, 2.5};
+    case SK_F64: return bm >= 128 ? Model{13.8, 0.0, 2.22, 5.56} : Model{8.9, 0.0, 0.82, 1.69};
+    case SK_F8_E4M3: return bm >= 256 ? Model{49.9, 0.0, 5.40, 6.91} : Model{0.0, 9.19, 1.49, 1.82};
+    default: return bm >= 256 ? Model{17.9, 0.0, 1.52, 6.24} : Model{0.0, 9.58, 0.74, 1.87};
     }
 }
 
