@@ -55,7 +55,7 @@ Model default_model(int ab, int bm) {
     switch (ab) {
     case SK_F64: return bm >= 128 ? Model{13.8, 0.0, 2.22, 5.56} : Model{8.9, 0.0, 0.82, 1.69};
     case SK_F8_E4M3: return bm >= 256 ? Model{49.9, 0.0, 5.40, 6.91} : Model{0.0, 9.19, 1.49, 1.82};
-    default: return bm >= 256 ? Model{17.9, 0.0, 1.52, 6.24} : Model{0.0, 9.58, 0.74, 1.87};
+    default: return bm >= 256 ? Model{17.3, 0.4, 1.52, 6.19} : Model{0.0, 12.4, 0.74, 1.05};
     }
 }
 

@@ -115,6 +115,9 @@ struct Cfg {
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
     // tile, whose register-staged MAC loop leaves no registers for it)
     static constexpr bool FIX_LDS = (RSETS == 2 || DMA) && !(D == Dt::F8 && BM >= 256);
+    // peers whose partial fragments are loaded together in the fixup (the
+    // 256x256 tiles have no registers for more than one at a time)
+    static constexpr int PEER_BATCH = BM >= 256 ? 1 : 4;
     using Acc = typename DtTraits<D>::Acc;
     using Frag = typename DtTraits<D>::Frag;
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
@@ -787,7 +790,20 @@ __device__ __forceinline__ typename C::Frag load_partial_frag(const char *slot, 
 template <class C>
 __device__ __forceinline__ typename C::Frag add_peers(typename C::Frag v, const char *slots, int p0, int p1,
                                                       int i, int j, int tid) {
-    for (int peer = p0; peer <= p1; ++peer)
+    // PEER_BATCH peers' fragments are loaded before they are added (one
+    // memory round trip per batch); the additions keep ascending order
+    int peer = p0;
+    if constexpr (C::PEER_BATCH > 1) {
+        for (; peer + C::PEER_BATCH - 1 <= p1; peer += C::PEER_BATCH) {
+            typename C::Frag x[C::PEER_BATCH];
+#pragma unroll
+            for (int u = 0; u < C::PEER_BATCH; ++u)
+                x[u] = load_partial_frag<C>(slots + (int64_t)(peer + u) * C::SLOT_BYTES, i, j, tid);
+#pragma unroll
+            for (int u = 0; u < C::PEER_BATCH; ++u) v = v + x[u];
+        }
+    }
+    for (; peer <= p1; ++peer)
         v = v + load_partial_frag<C>(slots + (int64_t)peer * C::SLOT_BYTES, i, j, tid);
     return v;
 }
