@@ -101,20 +101,15 @@ struct Cfg {
     static constexpr int FRAG_N = DtTraits<D>::FRAG_N;
     static constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    static constexpr int LDS = 2 * STAGE;
-    // register staging sets: with two, the global loads of k-tile i+2 are
-    // issued while k-tile i+1 (loaded one k-tile earlier) goes to LDS, so a
-    // load has about two k-tiles of MFMA work to arrive.  The 256x256 FP8
-    // tile has no registers to spare for the second set.
-    static constexpr int RSETS = (D == Dt::F8 && BM >= 256) ? 1 : 2;
-    // FP16/BF16/FP8 operands go global -> LDS directly (LDS-DMA buffer
-    // loads); an operand contiguous along m (n) keeps its natural layout in
-    // LDS and is transposed by the LDS transpose reads that build its
-    // fragments (16-bit or 8-bit forms).
-    static constexpr bool DMA = D == Dt::F16 || D == Dt::BF16 || D == Dt::F8;
+    // LDS k-tile buffers: FP64 keeps three (its k-tiles carry half the bytes
+    // of a 16-bit one for the same MFMA time, so its loads need two k-tiles
+    // of lead to hide their latency; one workgroup per CU leaves the room)
+    static constexpr int NSTAGE = D == Dt::F64 ? 3 : 2;
+    static constexpr int LDS = NSTAGE * STAGE;
+    static constexpr int DMA_PER_KTILE = BM / 32 + BN / 32;   // LDS-DMA loads per wave per k-tile
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
-    // tile, whose register-staged MAC loop leaves no registers for it)
-    static constexpr bool FIX_LDS = (RSETS == 2 || DMA) && !(D == Dt::F8 && BM >= 256);
+    // tile, whose transpose-read fragments leave no registers for it)
+    static constexpr bool FIX_LDS = !(D == Dt::F8 && BM >= 256);
     // peers whose partial fragments are loaded together in the fixup (the
     // 256x256 tiles have no registers for more than one at a time)
     static constexpr int PEER_BATCH = BM >= 256 ? 1 : 4;
@@ -137,141 +132,12 @@ __device__ __forceinline__ uint32_t lds_off(uint32_t row, uint32_t chunk) {
 }
 
 // ---------------------------------------------------------------------------
-// global -> register -> LDS staging of one operand tile (ROWS x BK)
+// global -> LDS staging of one operand tile (ROWS x BK) with LDS-DMA loads
 //
 // The operand is seen as a ROWS x k matrix X with element (r, p) at
-// KC ? r*ld + p : p*ld + r.  Every thread issues ROWS/32 16-byte loads per
-// k-tile whichever way X is stored.
-// ---------------------------------------------------------------------------
-template <class C, int ROWS, bool KC>
-struct Stage {
-    static constexpr int NL = ROWS / 32;            // loads per thread
-    static constexpr int E = C::E, VEC = C::VEC, BK = C::BK;
-    // contiguous-along-mn layout: a thread loads L k-rows of VEC elements
-    static constexpr int L = NL;
-    static constexpr int KB = BK / L;               // k-blocks (threads) per mn block
-    static constexpr int PIECE = L * E;             // bytes per mn-row piece
-
-    // Load i of k-tile kt reads 16 bytes at ub + kt*ustep + i*ustride + voff
-    // through a buffer resource: the base, k-tile step and load stride are
-    // uniform (scalar registers), the lane offset is one 32-bit VGPR, and a
-    // lane whose data lie outside the matrix gets an offset past the
-    // resource's range, which the hardware returns as zeros.
-    const char *ub;
-    int64_t ustep;
-    uint32_t ustride;
-    uint32_t voff;
-    int rows_valid;        // number of valid leading loads (row edge), KC only
-    bool mn_valid;         // !KC: this thread's mn block lies inside the matrix
-    int kofs;              // k offset (elements) of this thread's first load within a k-tile
-    uint32_t lds0;         // LDS offset of the first store (KC) / row base (!KC)
-    u32x4 r[C::RSETS][NL];
-
-    static constexpr uint32_t OOB = 0x80000000u;
-
-    __device__ __forceinline__ void init(const void *ptr, int64_t ld, int row0, int rows_total,
-                                         int tid) {
-        const char *p = (const char *)ptr;
-        if constexpr (KC) {
-            const int rr = tid >> 3, c = tid & 7;
-            ub = p + (int64_t)row0 * ld * E;
-            ustep = (int64_t)BK * E;
-            ustride = (uint32_t)(32 * ld * E);
-            voff = (uint32_t)(((int64_t)rr * ld + c * VEC) * E);
-            const int rem = rows_total - row0 - rr;     // rows left for this thread
-            rows_valid = rem <= 0 ? 0 : (rem + 31) / 32;
-            kofs = c * VEC;
-            lds0 = lds_off(rr, c);
-        } else {
-            const int kb = tid % KB, mb = tid / KB;
-            ub = p + (int64_t)row0 * E;
-            ustep = (int64_t)BK * ld * E;
-            ustride = (uint32_t)(ld * E);
-            voff = (uint32_t)(((int64_t)(kb * L) * ld + mb * VEC) * E);
-            mn_valid = row0 + mb * VEC < rows_total;
-            kofs = kb * L;
-            lds0 = (uint32_t)(mb * VEC);                // first row of the block
-        }
-    }
-
-    // Issue the loads of k-tile kt into register set S.  Out-of-range data are zero.
-    template <int S>
-    __device__ __forceinline__ void load(int kt, int K, bool interior) {
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
-        if constexpr (KC) {
-            const bool kv = interior || kt * BK + kofs < K;
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const uint32_t o = (interior || (kv && i < rows_valid)) ? voff : OOB;
-                r[S][i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, i * ustride, 0));
-            }
-        } else {
-            const int k0 = kt * BK + kofs;
-#pragma unroll
-            for (int j = 0; j < NL; ++j) {
-                const uint32_t o = (interior || (mn_valid && k0 + j < K)) ? voff : OOB;
-                r[S][j] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, j * ustride, 0));
-            }
-        }
-    }
-
-    // element e (0..VEC-1) of loaded vector j of set S, as raw bits in the low E bytes
-    template <int S>
-    __device__ __forceinline__ uint32_t elem_bits(int j, int e) const {
-        if constexpr (E == 2) return (r[S][j][e >> 1] >> ((e & 1) * 16)) & 0xffffu;
-        else return (r[S][j][e >> 2] >> ((e & 3) * 8)) & 0xffu;
-    }
-
-    // Write register set S to an LDS stage.
-    template <int S>
-    __device__ __forceinline__ void store(char *lds) const {
-        if constexpr (KC) {
-#pragma unroll
-            for (int i = 0; i < NL; ++i) *(u32x4 *)(lds + lds0 + i * 32 * 128) = r[S][i];
-        } else {
-            const int kb_byte = kofs * E;               // byte offset of the piece in a row
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const uint32_t row = lds0 + e;
-                if constexpr (E == 8) {
-                    // f64: element e of each load is one double (two words)
-#pragma unroll
-                    for (int s = 0; s < PIECE / 16; ++s) {
-                        u32x4 w;
-                        w[0] = r[S][2 * s][2 * e];
-                        w[1] = r[S][2 * s][2 * e + 1];
-                        w[2] = r[S][2 * s + 1][2 * e];
-                        w[3] = r[S][2 * s + 1][2 * e + 1];
-                        *(u32x4 *)(lds + lds_off(row, (kb_byte >> 4) + s)) = w;
-                    }
-                } else {
-                    constexpr int NW = PIECE / 4;       // words in the piece
-                    constexpr int PER = 4 / E;          // elements per word
-                    uint32_t w[NW];
-#pragma unroll
-                    for (int q = 0; q < NW; ++q) {
-                        uint32_t v = 0;
-#pragma unroll
-                        for (int b = 0; b < PER; ++b) v |= elem_bits<S>(q * PER + b, e) << (b * 8 * E);
-                        w[q] = v;
-                    }
-                    char *dst = lds + lds_off(row, kb_byte >> 4) + (kb_byte & 15);
-                    if constexpr (NW == 4) *(u32x4 *)dst = u32x4{w[0], w[1], w[2], w[3]};
-                    else if constexpr (NW == 2) *(u32x2 *)dst = u32x2{w[0], w[1]};
-                    else *(uint32_t *)dst = w[0];
-                }
-            }
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// global -> LDS staging of one 16-bit operand tile with LDS-DMA loads
-//
-// Each wave instruction moves 1 KiB: lane L's 16 bytes land at the wave's
-// LDS block + 16 L, so the XOR swizzles are applied by choosing which global
-// chunk each lane fetches.
+// KC ? r*ld + p : p*ld + r.  Each wave instruction moves 1 KiB: lane L's 16
+// bytes land at the wave's LDS block + 16 L, so the XOR swizzles are applied
+// by choosing which global chunk each lane fetches.
 //  KC (rows x k, k contiguous): the block is 8 rows of 128 bytes in the
 //    lds_off layout; lane L fetches row L/8, chunk (L%8) ^ ((row/2) % 8).
 //  !KC (k x rows, rows contiguous): LDS k-row p holds the tile's ROWS
@@ -281,13 +147,14 @@ struct Stage {
 // deposit zeros.
 // ---------------------------------------------------------------------------
 // Chunk swizzle of k-row p in the !KC (natural) layout, chosen so that the
-// transpose reads of one fragment -- 16-bit: 4 consecutive k-rows x 32
-// bytes per 16 lanes; 8-bit: 8 consecutive k-rows x 16 bytes -- hit every
-// bank once per 256 bytes.  A k-row of 256 bytes fills the 64 banks; one of
-// 128 bytes shares them with its neighbour.
+// fragment reads -- 16-bit transpose reads: 4 consecutive k-rows x 32 bytes
+// per 16 lanes; 8-bit: 8 consecutive k-rows x 16 bytes; FP64: 4 k-rows two
+// apart x 128 bytes -- hit every bank once per 256 bytes.  A k-row of 256
+// bytes fills the 64 banks; one of 128 bytes shares them with its neighbour.
 template <int E, int ROWS>
 __device__ __forceinline__ int nkc_swizzle(int p) {
-    if constexpr (E == 2) return 4 * (p & 3);
+    if constexpr (E == 8) return 8 * ((p >> 1) & 1);
+    else if constexpr (E == 2) return 4 * (p & 3);
     else if constexpr (ROWS * E >= 256) return 2 * (p & 7);
     else return 2 * ((p >> 1) & 3);
 }
@@ -298,7 +165,7 @@ struct StageDma {
     static constexpr int E = C::E, VEC = C::VEC, BK = C::BK;
     static constexpr int CPR = ROWS * E / 16;       // !KC: chunks per k-row
     static constexpr int KR = 1024 / (ROWS * E);    // !KC: k-rows per 1 KiB block
-    static_assert((E == 2 || E == 1) && BK * E == 128, "16- or 8-bit operands, 128-byte k rows");
+    static_assert(BK * E == 128 && KR >= 1, "128-byte k rows, whole k-rows per 1 KiB block");
     static constexpr uint32_t OOB = 0x80000000u;
     const char *ub;
     int64_t ustep;
@@ -361,8 +228,24 @@ struct StageDma {
     }
 };
 
-// Wait for this wave's LDS-DMA loads to land.
+// Wait for this wave's LDS-DMA loads to land: all of them, or all but the
+// newest N (vector-memory loads complete in issue order).
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+template <int N>
+__device__ __forceinline__ void wait_dma_but() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    // s_waitcnt encoding: vmcnt[3:0] and [15:14], expcnt [6:4] = 7 and
+    // lgkmcnt [11:8] = 15 (no wait on those)
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+    asm volatile("" ::: "memory");
+}
+
+template <int I>
+__device__ __forceinline__ char *lds_buf(char *b0, char *b1, char *b2) {
+    if constexpr (I == 0) return b0;
+    else if constexpr (I == 1) return b1;
+    else return b2;
+}
 
 // ---------------------------------------------------------------------------
 // MFMA operand fragments
@@ -436,14 +319,36 @@ __device__ __forceinline__ void frag_tr8(u32x4 (&out)[2], const char *op, uint32
     out[1] = u32x4{w[4], w[5], w[6], w[7]};
 }
 
+// One FP64 MFMA operand fragment from a !KC operand stage: lane l (row
+// base + l%16, group q = l/16) needs k = 8ks + 2q and 8ks + 2q + 1 (one per
+// MFMA of the pair); 16 lanes read 128 consecutive bytes of one k-row.
+template <class C, int ROWS>
+__device__ __forceinline__ u32x4 frag_f64_nkc(const char *op, uint32_t base, int ks, int lane) {
+    constexpr int RB = ROWS * 8;
+    const int q = lane >> 4;
+    const uint32_t r = base + (lane & 15);
+    u32x2 h[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int p = 8 * ks + 2 * q + e;
+        const uint32_t off = (uint32_t)p * RB + (((r >> 1) ^ (uint32_t)nkc_swizzle<8, ROWS>(p)) << 4) + (r & 1) * 8;
+        h[e] = *(const u32x2 *)(op + off);
+    }
+    return u32x4{h[0][0], h[0][1], h[1][0], h[1][1]};
+}
+
 template <class C>
 __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const char *ldsB, uint32_t arow,
                                            uint32_t brow, int ks, int q) {
-    if constexpr (C::DMA && !C::AKC && C::DT == Dt::F8) {
+    if constexpr (!C::AKC && C::DT == Dt::F64) {
+        const int lane = (int)(arow % 16) + 16 * q;
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) f.a[i][0] = frag_f64_nkc<C, C::BM>(ldsA, arow - arow % 16 + i * C::MT, ks, lane);
+    } else if constexpr (!C::AKC && C::DT == Dt::F8) {
         const int lane = (int)(arow % 32) + 32 * q;
 #pragma unroll
         for (int i = 0; i < C::FM; ++i) frag_tr8<C, C::BM>(f.a[i], ldsA, arow - arow % 32 + i * C::MT, ks, lane);
-    } else if constexpr (C::DMA && !C::AKC) {
+    } else if constexpr (!C::AKC) {
         const int lane = (int)(arow % 32) + 32 * q;
 #pragma unroll
         for (int i = 0; i < C::FM; ++i) f.a[i][0] = frag_tr<C, C::BM>(ldsA, arow - arow % 32 + i * C::MT, ks, lane);
@@ -455,11 +360,15 @@ __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const c
             for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
         }
     }
-    if constexpr (C::DMA && !C::BKC && C::DT == Dt::F8) {
+    if constexpr (!C::BKC && C::DT == Dt::F64) {
+        const int lane = (int)(brow % 16) + 16 * q;
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) f.b[j][0] = frag_f64_nkc<C, C::BN>(ldsB, brow - brow % 16 + j * C::MT, ks, lane);
+    } else if constexpr (!C::BKC && C::DT == Dt::F8) {
         const int lane = (int)(brow % 32) + 32 * q;
 #pragma unroll
         for (int j = 0; j < C::FN; ++j) frag_tr8<C, C::BN>(f.b[j], ldsB, brow - brow % 32 + j * C::MT, ks, lane);
-    } else if constexpr (C::DMA && !C::BKC) {
+    } else if constexpr (!C::BKC) {
         const int lane = (int)(brow % 32) + 32 * q;
 #pragma unroll
         for (int j = 0; j < C::FN; ++j) f.b[j][0] = frag_tr<C, C::BN>(ldsB, brow - brow % 32 + j * C::MT, ks, lane);
@@ -510,37 +419,38 @@ __device__ __forceinline__ void mfma_step(typename C::Frag (&acc)[C::FM][C::FN],
 // ---------------------------------------------------------------------------
 // The MAC loop over iterations [it0, it1) of one tile (Algorithm 3)
 //
-// Per k-tile i: the global loads of k-tile i + RSETS are issued first (into
-// the register set that k-tile i came through); the k-steps run with their
+// Per k-tile i: the LDS-DMA loads of k-tile i+1 go to the other LDS buffer
+// (free since the last barrier); the k-steps of k-tile i run with their
 // operand fragments double-buffered in registers (the reads of step s+1
-// overlap the MFMAs of step s); k-tile i+1, already in registers, is written
-// to the other LDS buffer; one barrier; then the first fragments of k-tile
-// i+1 are read.
+// overlap the MFMAs of step s); the wave waits for its loads, one barrier,
+// then the first fragments of k-tile i+1 are read.
 // ---------------------------------------------------------------------------
 template <class C>
 struct Ctx {
-    typename std::conditional<C::DMA, StageDma<C, C::BM, C::AKC>, Stage<C, C::BM, C::AKC>>::type sa;
-    typename std::conditional<C::DMA, StageDma<C, C::BN, C::BKC>, Stage<C, C::BN, C::BKC>>::type sb;
+    StageDma<C, C::BM, C::AKC> sa;
+    StageDma<C, C::BN, C::BKC> sb;
 };
 
-// One k-tile of a DMA configuration: the LDS-DMA loads of k-tile i+1 go to
-// the other LDS buffer (free since the last barrier) while the k-steps of
-// k-tile i run; the wave waits for its loads, one barrier, then the first
-// fragments of k-tile i+1 are read.  P: which buffer holds k-tile i.  The
-// two buffers are distinct LDS objects, so the compiler can tell that the
-// fragment reads of one never wait for the DMA writes into the other.
+// One k-tile.  FIRST: the segment's first k-tile, whose first k-step starts
+// the accumulators from zero.  P: which buffer holds k-tile i.  With
+// NSTAGE buffers the loads run NSTAGE - 1 k-tiles ahead.  The buffers are
+// distinct LDS objects, so the compiler can tell that the fragment reads of
+// one never wait for the DMA writes into another.
 template <class C, bool FIRST, int P>
 __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
-                                          char *lds0, char *lds1, int it, int it1, bool rows_in, int kfull, int K,
-                                          uint32_t arow, uint32_t brow, int q) {
+                                          char *lds0, char *lds1, char *lds2, int it, int it1, bool rows_in,
+                                          int kfull, int K, uint32_t arow, uint32_t brow, int q) {
     constexpr int NSUB = Frag<C>::NSUB;
+    constexpr int NS = C::NSTAGE, LA = NS - 1;
+    const char *st = lds_buf<P>(lds0, lds1, lds2);
+    char *nx = lds_buf<(P + 1) % NS>(lds0, lds1, lds2);
+    char *ld = lds_buf<(P + LA) % NS>(lds0, lds1, lds2);
     const bool more = it + 1 < it1;
-    const char *st = P ? lds1 : lds0;
-    char *nx = P ? lds0 : lds1;
-    if (more) {
-        const bool in = rows_in && it + 1 < kfull;
-        cx.sa.issue(nx, it + 1, K, in);
-        cx.sb.issue(nx + C::A_BYTES, it + 1, K, in);
+    const bool ahead = it + LA < it1;
+    if (ahead) {
+        const bool in = rows_in && it + LA < kfull;
+        cx.sa.issue(ld, it + LA, K, in);
+        cx.sb.issue(ld + C::A_BYTES, it + LA, K, in);
     }
 #pragma unroll
     for (int ks = 0; ks < NSUB; ++ks) {
@@ -548,42 +458,13 @@ __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename 
         if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
         else mfma_step<C, false>(acc, f[ks & 1]);
     }
-    wait_dma();
-    __syncthreads();
-    if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
-}
-
-// One k-tile.  FIRST: the segment's first k-tile, whose first k-step starts
-// the accumulators from zero.  P: parity of the k-tile within the segment,
-// which selects the register set loaded now (and, with two sets, the other
-// one is written to LDS).
-template <class C, bool FIRST, int P>
-__device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
-                                      char *lds0, char *lds1, int it, int it0, int it1, bool rows_in, int kfull,
-                                      int K, uint32_t arow, uint32_t brow, int q) {
-    constexpr int NSUB = Frag<C>::NSUB;
-    constexpr int LD = C::RSETS == 2 ? P : 0;          // set receiving the new loads
-    constexpr int ST = C::RSETS == 2 ? P ^ 1 : 0;      // set written to LDS
-    // with two register sets the k-tiles run in pairs and P is the buffer
-    const int cur = C::RSETS == 2 ? P : (it - it0) & 1;
-    const bool more = it + 1 < it1;
-    const int ahead = it + C::RSETS;
-    if (ahead < it1) {
-        const bool in = rows_in && ahead < kfull;
-        cx.sa.template load<LD>(ahead, K, in);
-        cx.sb.template load<LD>(ahead, K, in);
-    }
-    const char *st = cur ? lds1 : lds0;
-    char *nx = cur ? lds0 : lds1;
-#pragma unroll
-    for (int ks = 0; ks < NSUB; ++ks) {
-        if (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
-        if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
-        else mfma_step<C, false>(acc, f[ks & 1]);
-    }
-    if (more) {
-        cx.sa.template store<ST>(nx);
-        cx.sb.template store<ST>(nx + C::A_BYTES);
+    // k-tile i+1 must have landed; with three buffers the loads of k-tile
+    // i+2 (the newest) may stay in flight
+    if constexpr (LA > 1) {
+        if (ahead) wait_dma_but<C::DMA_PER_KTILE>();
+        else wait_dma();
+    } else {
+        wait_dma();
     }
     __syncthreads();
     if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
@@ -592,7 +473,7 @@ __device__ __forceinline__ void ktile(Ctx<C> &cx, Frag<C> (&f)[2], typename C::F
 template <class C>
 __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int it0, int it1,
                                          typename C::Frag (&acc)[C::FM][C::FN], char *lds0, char *lds1,
-                                         int tid) {
+                                         char *lds2, int tid) {
     if (it0 >= it1) {
         // an empty range (never produced by the planner, which sends k == 0
         // work to the C = beta*C kernel): zero accumulators via a
@@ -619,47 +500,42 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
     cx.sb.init(P.B, P.ldb, col0, P.n, tid);
     const bool rows_in = (row0 + C::BM <= P.m) && (col0 + C::BN <= P.n);
     const int kfull = P.k / C::BK;                 // k-tiles with no k edge
-    if constexpr (C::DMA) {
-        const bool in = rows_in && it0 < kfull;
-        cx.sa.issue(lds0, it0, P.k, in);
-        cx.sb.issue(lds0 + C::A_BYTES, it0, P.k, in);
-        wait_dma();
-        __syncthreads();
-        Frag<C> f[2];
-        read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
-        ktile_dma<C, true, 0>(cx, f, acc, lds0, lds1, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-        // k-tiles in pairs so the LDS buffer of each is a constant
-        for (int it = it0 + 1; it < it1; it += 2) {
-            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, it, it1, rows_in, kfull, P.k, arow, brow, q);
-            if (it + 1 < it1)
-                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, it + 1, it1, rows_in, kfull, P.k, arow, brow, q);
+    const bool in = rows_in && it0 < kfull;
+    cx.sa.issue(lds0, it0, P.k, in);
+    cx.sb.issue(lds0 + C::A_BYTES, it0, P.k, in);
+    if constexpr (C::NSTAGE == 3) {
+        if (it0 + 1 < it1) {
+            const bool in1 = rows_in && it0 + 1 < kfull;
+            cx.sa.issue(lds1, it0 + 1, P.k, in1);
+            cx.sb.issue(lds1 + C::A_BYTES, it0 + 1, P.k, in1);
+            wait_dma_but<C::DMA_PER_KTILE>();
+        } else {
+            wait_dma();
         }
     } else {
-        const bool in = rows_in && it0 < kfull;
-        cx.sa.template load<0>(it0, P.k, in);
-        cx.sb.template load<0>(it0, P.k, in);
-        if (C::RSETS == 2 && it0 + 1 < it1) {
-            const bool in1 = rows_in && it0 + 1 < kfull;
-            cx.sa.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
-            cx.sb.template load<C::RSETS - 1>(it0 + 1, P.k, in1);
-        }
-        cx.sa.template store<0>(lds0);
-        cx.sb.template store<0>(lds0 + C::A_BYTES);
-        __syncthreads();
-        Frag<C> f[2];
-        read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
-        ktile<C, true, 0>(cx, f, acc, lds0, lds1, it0, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-        if constexpr (C::RSETS == 2) {
-            // k-tiles in pairs so the register-set parity is a constant
-            for (int it = it0 + 1; it < it1; it += 2) {
-                ktile<C, false, 1>(cx, f, acc, lds0, lds1, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-                if (it + 1 < it1)
-                    ktile<C, false, 0>(cx, f, acc, lds0, lds1, it + 1, it0, it1, rows_in, kfull, P.k, arow, brow,
+        wait_dma();
+    }
+    __syncthreads();
+    Frag<C> f[2];
+    read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
+    ktile_dma<C, true, 0>(cx, f, acc, lds0, lds1, lds2, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+    // k-tiles in groups of NSTAGE so the LDS buffer of each is a constant
+    if constexpr (C::NSTAGE == 3) {
+        for (int it = it0 + 1; it < it1; it += 3) {
+            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, lds2, it, it1, rows_in, kfull, P.k, arow, brow, q);
+            if (it + 1 < it1)
+                ktile_dma<C, false, 2>(cx, f, acc, lds0, lds1, lds2, it + 1, it1, rows_in, kfull, P.k, arow, brow,
                                        q);
-            }
-        } else {
-            for (int it = it0 + 1; it < it1; ++it)
-                ktile<C, false, 0>(cx, f, acc, lds0, lds1, it, it0, it1, rows_in, kfull, P.k, arow, brow, q);
+            if (it + 2 < it1)
+                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, lds2, it + 2, it1, rows_in, kfull, P.k, arow, brow,
+                                       q);
+        }
+    } else {
+        for (int it = it0 + 1; it < it1; it += 2) {
+            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, lds2, it, it1, rows_in, kfull, P.k, arow, brow, q);
+            if (it + 1 < it1)
+                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, lds2, it + 1, it1, rows_in, kfull, P.k, arow, brow,
+                                       q);
         }
     }
 }
@@ -1144,6 +1020,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     // the two k-tile buffers of the MAC loop
     __shared__ __attribute__((aligned(16))) char lds0[C::STAGE];
     __shared__ __attribute__((aligned(16))) char lds1[C::STAGE];
+    __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE == 3 ? C::STAGE : 16];
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
     int x = b;
@@ -1203,7 +1080,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         int tid = tid0;
         asm volatile("" : "+v"(tid));
         typename C::Frag acc[C::FM][C::FN];
-        mac_loop<C>(P, tm, tn, k0, k1, acc, lds0, lds1, tid);
+        mac_loop<C>(P, tm, tn, k0, k1, acc, lds0, lds1, lds2, tid);
         if (!started) {
             store_partial<C>((char *)p.partials + (int64_t)x * C::SLOT_BYTES, acc, tid);
             signal_flag(p.flags + x * FLAG_STRIDE, tid);
