@@ -93,20 +93,27 @@ struct Cfg {
     static constexpr bool AKC = AKC_, BKC = BKC_, GROUPED = GROUPED_;
     static constexpr int E = DtTraits<D>::E;
     static constexpr int VEC = 16 / E;          // elements per 16-byte load
-    static constexpr int BK = 8 * VEC;          // an LDS row = 8 chunks = 128 B
+    static constexpr int BK = 8 * VEC;          // MAC-loop iteration: 128 bytes of k
     static constexpr int BM = BM_, BN = BN_;
+    // staged k-tile: KROW bytes of k per LDS row (64-byte rows -- half
+    // iterations, four buffers -- were measured slower for the 256x256
+    // 16-bit tile: twice the barriers, and the extra lead bought nothing)
+    static constexpr int KROW = 128;
+    static constexpr int BKS = KROW / E;        // k per staged k-tile
+    static constexpr int SUB = BK / BKS;        // staged k-tiles per MAC-loop iteration
     static constexpr int WTM = BM / 2, WTN = BN / 2;   // 2 x 2 waves
     static constexpr int MT = DtTraits<D>::MT;
     static constexpr int FM = WTM / MT, FN = WTN / MT;
     static constexpr int FRAG_N = DtTraits<D>::FRAG_N;
-    static constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
+    static constexpr int A_BYTES = BM * KROW, B_BYTES = BN * KROW;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    // LDS k-tile buffers: FP64 keeps three (its k-tiles carry half the bytes
-    // of a 16-bit one for the same MFMA time, so its loads need two k-tiles
-    // of lead to hide their latency; one workgroup per CU leaves the room)
-    static constexpr int NSTAGE = D == Dt::F64 ? 3 : 2;
+    // LDS k-tile buffers.  FP64 keeps three (its k-tiles carry half the
+    // bytes of a 16-bit one for the same MFMA time, so its loads need two
+    // k-tiles of lead to hide their latency; one workgroup per CU leaves the
+    // room).
+    static constexpr int NSTAGE = D == Dt::F64 ? 3 : (KROW == 64 ? 4 : 2);
     static constexpr int LDS = NSTAGE * STAGE;
-    static constexpr int DMA_PER_KTILE = BM / 32 + BN / 32;   // LDS-DMA loads per wave per k-tile
+    static constexpr int DMA_PER_KTILE = STAGE / 4096;   // LDS-DMA loads per wave per staged k-tile
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
     // tile, whose transpose-read fragments leave no registers for it)
     static constexpr bool FIX_LDS = !(D == Dt::F8 && BM >= 256);
@@ -121,14 +128,15 @@ struct Cfg {
     static_assert(BM * BN == THREADS * ACC_N, "accumulator split");
 };
 
-// LDS byte offset of 16-byte chunk c of row r (128-byte rows, XOR swizzle).
-// The LDS serves a 16-byte-per-lane access 16 lanes per cycle across 64
-// banks (256 bytes): two consecutive 128-byte rows share one bank row, so
-// the swizzle key is row/2.  Then 16 lanes reading the same chunk of 16
-// consecutive rows, and 16 lanes writing 8 chunks of each of 2 consecutive
-// rows, all hit distinct banks.
+// LDS byte offset of 16-byte chunk c of row r (KROW-byte rows, XOR
+// swizzle).  The LDS serves a 16-byte-per-lane access 16 lanes per cycle
+// across 64 banks (256 bytes): 256/KROW consecutive rows share one bank
+// row, so the swizzle key is row/(256/KROW).  Then 16 lanes reading the
+// same chunk of 16 consecutive rows all hit distinct banks.
+template <int KROW>
 __device__ __forceinline__ uint32_t lds_off(uint32_t row, uint32_t chunk) {
-    return row * 128u + (((chunk ^ (row >> 1)) & 7u) << 4);
+    if constexpr (KROW == 128) return row * 128u + (((chunk ^ (row >> 1)) & 7u) << 4);
+    else return row * 64u + (((chunk ^ (row >> 2)) & 3u) << 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -138,8 +146,9 @@ __device__ __forceinline__ uint32_t lds_off(uint32_t row, uint32_t chunk) {
 // KC ? r*ld + p : p*ld + r.  Each wave instruction moves 1 KiB: lane L's 16
 // bytes land at the wave's LDS block + 16 L, so the XOR swizzles are applied
 // by choosing which global chunk each lane fetches.
-//  KC (rows x k, k contiguous): the block is 8 rows of 128 bytes in the
-//    lds_off layout; lane L fetches row L/8, chunk (L%8) ^ ((row/2) % 8).
+//  KC (rows x k, k contiguous): the block is 1024/KROW rows of KROW bytes in
+//    the lds_off layout; lane L fetches row L/(KROW/16), chunk
+//    (L % (KROW/16)) ^ swizzle(row).
 //  !KC (k x rows, rows contiguous): LDS k-row p holds the tile's ROWS
 //    values (E*ROWS bytes) with 16-byte chunk c at slot c ^ sw(p) (see
 //    nkc_swizzle); the block is 1024 / (E*ROWS) k-rows.
@@ -161,11 +170,13 @@ __device__ __forceinline__ int nkc_swizzle(int p) {
 
 template <class C, int ROWS, bool KC>
 struct StageDma {
-    static constexpr int NL = ROWS / 32;            // loads per wave per k-tile
-    static constexpr int E = C::E, VEC = C::VEC, BK = C::BK;
+    static constexpr int E = C::E, VEC = C::VEC, BK = C::BKS, KROW = C::KROW;
+    static constexpr int NL = ROWS * KROW / 4096;   // loads per wave per staged k-tile
+    static constexpr int RPB = 1024 / KROW;         // KC: rows per 1 KiB block
+    static constexpr int LPR = KROW / 16;           // KC: lanes per row
     static constexpr int CPR = ROWS * E / 16;       // !KC: chunks per k-row
     static constexpr int KR = 1024 / (ROWS * E);    // !KC: k-rows per 1 KiB block
-    static_assert(BK * E == 128 && KR >= 1, "128-byte k rows, whole k-rows per 1 KiB block");
+    static_assert(BK * E == KROW && KR >= 1 && NL >= 1, "whole rows per 1 KiB block");
     static constexpr uint32_t OOB = 0x80000000u;
     const char *ub;
     int64_t ustep;
@@ -180,16 +191,18 @@ struct StageDma {
         const char *p = (const char *)ptr;
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6), L = tid & 63;
         if constexpr (KC) {
-            const int rr = 8 * w + (L >> 3);
-            const int c = (L & 7) ^ ((4 * w + (L >> 4)) & 7);
+            // rows rr + 4*RPB*i; the swizzle key is the same for every i
+            const int rr = RPB * w + L / LPR;
+            const int key = KROW == 128 ? (rr >> 1) & 7 : (rr >> 2) & 3;
+            const int c = (L % LPR) ^ key;
             ub = p + (int64_t)row0 * ld * E;
             ustep = (int64_t)BK * E;
-            ustride = (uint32_t)(32 * ld * E);
+            ustride = (uint32_t)(4 * RPB * ld * E);
             voff = (uint32_t)(((int64_t)rr * ld + c * VEC) * E);
             const int rem = rows_total - row0 - rr;
-            rows_valid = rem <= 0 ? 0 : (rem + 31) / 32;
+            rows_valid = rem <= 0 ? 0 : (rem + 4 * RPB - 1) / (4 * RPB);
             kofs = c * VEC;
-            lds_w = (uint32_t)(8 * w * 128);
+            lds_w = (uint32_t)(w * 1024);
         } else {
             const int pr = w * KR + L / CPR;            // k-row of load 0 within the k-tile
             const int c = (L % CPR) ^ nkc_swizzle<E, ROWS>(pr);
@@ -211,7 +224,7 @@ struct StageDma {
     __device__ __forceinline__ void issue(char *lds, int kt, int K, bool interior) const {
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
-        constexpr int BLK = KC ? 32 * 128 : 4096;       // LDS bytes between a wave's blocks
+        constexpr int BLK = 4096;                       // LDS bytes between a wave's blocks
         if (interior) {
 #pragma unroll
             for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, voff, i * ustride);
@@ -240,11 +253,36 @@ __device__ __forceinline__ void wait_dma_but() {
     asm volatile("" ::: "memory");
 }
 
-template <int I>
-__device__ __forceinline__ char *lds_buf(char *b0, char *b1, char *b2) {
-    if constexpr (I == 0) return b0;
-    else if constexpr (I == 1) return b1;
-    else return b2;
+// The MAC loop's LDS k-tile buffers: separate LDS objects (NSTAGE of them
+// in use), selected by compile-time index.
+struct LdsBufs {
+    char *b0, *b1, *b2, *b3;
+    template <int I>
+    __device__ __forceinline__ char *get() const {
+        if constexpr (I == 0) return b0;
+        else if constexpr (I == 1) return b1;
+        else if constexpr (I == 2) return b2;
+        else return b3;
+    }
+};
+
+// Wait until at most n (< LA) staged k-tiles of this wave's loads are
+// still in flight (each staged k-tile is DPK loads).
+template <int LA, int DPK>
+__device__ __forceinline__ void wait_landed(int n) {
+    if constexpr (LA >= 3) {
+        if (n >= 2) {
+            wait_dma_but<2 * DPK>();
+            return;
+        }
+    }
+    if constexpr (LA >= 2) {
+        if (n >= 1) {
+            wait_dma_but<DPK>();
+            return;
+        }
+    }
+    wait_dma();
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +300,8 @@ __device__ __forceinline__ char *lds_buf(char *b0, char *b1, char *b2) {
 template <class C>
 struct Frag {
     static constexpr int CPM = (C::DT == Dt::F8) ? 2 : 1;          // chunks per lane per operand
-    static constexpr int NSUB = (C::DT == Dt::F64) ? 2 : 8 / (2 * CPM);
+    static constexpr int CHUNKS = C::KROW / 16;                     // chunks per staged LDS row
+    static constexpr int NSUB = (C::DT == Dt::F64) ? CHUNKS / 4 : CHUNKS / (2 * CPM);   // k-steps per staged k-tile
     u32x4 a[C::FM][CPM], b[C::FN][CPM];
 };
 
@@ -357,7 +396,7 @@ __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const c
         for (int s = 0; s < Frag<C>::CPM; ++s) {
             const int c = frag_chunk<C>(ks, q, s);
 #pragma unroll
-            for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off(arow + i * C::MT, c));
+            for (int i = 0; i < C::FM; ++i) f.a[i][s] = *(const u32x4 *)(ldsA + lds_off<C::KROW>(arow + i * C::MT, c));
         }
     }
     if constexpr (!C::BKC && C::DT == Dt::F64) {
@@ -377,7 +416,7 @@ __device__ __forceinline__ void read_frags(Frag<C> &f, const char *ldsA, const c
         for (int s = 0; s < Frag<C>::CPM; ++s) {
             const int c = frag_chunk<C>(ks, q, s);
 #pragma unroll
-            for (int j = 0; j < C::FN; ++j) f.b[j][s] = *(const u32x4 *)(ldsB + lds_off(brow + j * C::MT, c));
+            for (int j = 0; j < C::FN; ++j) f.b[j][s] = *(const u32x4 *)(ldsB + lds_off<C::KROW>(brow + j * C::MT, c));
         }
     }
 }
@@ -431,23 +470,22 @@ struct Ctx {
     StageDma<C, C::BN, C::BKC> sb;
 };
 
-// One k-tile.  FIRST: the segment's first k-tile, whose first k-step starts
-// the accumulators from zero.  P: which buffer holds k-tile i.  With
-// NSTAGE buffers the loads run NSTAGE - 1 k-tiles ahead.  The buffers are
+// One staged k-tile.  FIRST: the segment's first, whose first k-step starts
+// the accumulators from zero.  P: which buffer holds it.  With NSTAGE
+// buffers the loads run NSTAGE - 1 staged k-tiles ahead.  The buffers are
 // distinct LDS objects, so the compiler can tell that the fragment reads of
 // one never wait for the DMA writes into another.
 template <class C, bool FIRST, int P>
 __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
-                                          char *lds0, char *lds1, char *lds2, int it, int it1, bool rows_in,
-                                          int kfull, int K, uint32_t arow, uint32_t brow, int q) {
+                                          const LdsBufs &bufs, int it, int it1, bool rows_in, int kfull, int K,
+                                          uint32_t arow, uint32_t brow, int q) {
     constexpr int NSUB = Frag<C>::NSUB;
     constexpr int NS = C::NSTAGE, LA = NS - 1;
-    const char *st = lds_buf<P>(lds0, lds1, lds2);
-    char *nx = lds_buf<(P + 1) % NS>(lds0, lds1, lds2);
-    char *ld = lds_buf<(P + LA) % NS>(lds0, lds1, lds2);
+    const char *st = bufs.template get<P>();
+    char *nx = bufs.template get<(P + 1) % NS>();
+    char *ld = bufs.template get<(P + LA) % NS>();
     const bool more = it + 1 < it1;
-    const bool ahead = it + LA < it1;
-    if (ahead) {
+    if (it + LA < it1) {
         const bool in = rows_in && it + LA < kfull;
         cx.sa.issue(ld, it + LA, K, in);
         cx.sb.issue(ld + C::A_BYTES, it + LA, K, in);
@@ -458,22 +496,17 @@ __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename 
         if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
         else mfma_step<C, false>(acc, f[ks & 1]);
     }
-    // k-tile i+1 must have landed; with three buffers the loads of k-tile
-    // i+2 (the newest) may stay in flight
-    if constexpr (LA > 1) {
-        if (ahead) wait_dma_but<C::DMA_PER_KTILE>();
-        else wait_dma();
-    } else {
-        wait_dma();
-    }
+    // staged k-tile it+1 must have landed; newer ones may stay in flight
+    const int newer = it1 - 1 - (it + 1) < LA - 1 ? it1 - 1 - (it + 1) : LA - 1;
+    wait_landed<LA, C::DMA_PER_KTILE>(newer);
     __syncthreads();
     if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
 }
 
 template <class C>
 __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int it0, int it1,
-                                         typename C::Frag (&acc)[C::FM][C::FN], char *lds0, char *lds1,
-                                         char *lds2, int tid) {
+                                         typename C::Frag (&acc)[C::FM][C::FN], const LdsBufs &bufs,
+                                         int tid) {
     if (it0 >= it1) {
         // an empty range (never produced by the planner, which sends k == 0
         // work to the C = beta*C kernel): zero accumulators via a
@@ -499,43 +532,34 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
     cx.sa.init(P.A, P.lda, row0, P.m, tid);
     cx.sb.init(P.B, P.ldb, col0, P.n, tid);
     const bool rows_in = (row0 + C::BM <= P.m) && (col0 + C::BN <= P.n);
-    const int kfull = P.k / C::BK;                 // k-tiles with no k edge
-    const bool in = rows_in && it0 < kfull;
-    cx.sa.issue(lds0, it0, P.k, in);
-    cx.sb.issue(lds0 + C::A_BYTES, it0, P.k, in);
-    if constexpr (C::NSTAGE == 3) {
-        if (it0 + 1 < it1) {
-            const bool in1 = rows_in && it0 + 1 < kfull;
-            cx.sa.issue(lds1, it0 + 1, P.k, in1);
-            cx.sb.issue(lds1 + C::A_BYTES, it0 + 1, P.k, in1);
-            wait_dma_but<C::DMA_PER_KTILE>();
-        } else {
-            wait_dma();
+    // the loop runs over staged k-tiles: SUB per MAC-loop iteration
+    const int s0 = it0 * C::SUB, s1 = it1 * C::SUB;
+    const int kfull = P.k / C::BKS;                // staged k-tiles with no k edge
+    constexpr int NS = C::NSTAGE, LA = NS - 1;
+    static_for<LA>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        if (s0 + j < s1) {
+            const bool in = rows_in && s0 + j < kfull;
+            cx.sa.issue(bufs.template get<j>(), s0 + j, P.k, in);
+            cx.sb.issue(bufs.template get<j>() + C::A_BYTES, s0 + j, P.k, in);
         }
-    } else {
-        wait_dma();
-    }
+    });
+    wait_landed<LA, C::DMA_PER_KTILE>(s1 - 1 - s0 < LA - 1 ? s1 - 1 - s0 : LA - 1);
     __syncthreads();
     Frag<C> f[2];
-    read_frags<C>(f[0], lds0, lds0 + C::A_BYTES, arow, brow, 0, q);
-    ktile_dma<C, true, 0>(cx, f, acc, lds0, lds1, lds2, it0, it1, rows_in, kfull, P.k, arow, brow, q);
-    // k-tiles in groups of NSTAGE so the LDS buffer of each is a constant
-    if constexpr (C::NSTAGE == 3) {
-        for (int it = it0 + 1; it < it1; it += 3) {
-            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, lds2, it, it1, rows_in, kfull, P.k, arow, brow, q);
-            if (it + 1 < it1)
-                ktile_dma<C, false, 2>(cx, f, acc, lds0, lds1, lds2, it + 1, it1, rows_in, kfull, P.k, arow, brow,
-                                       q);
-            if (it + 2 < it1)
-                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, lds2, it + 2, it1, rows_in, kfull, P.k, arow, brow,
-                                       q);
+    read_frags<C>(f[0], bufs.b0, bufs.b0 + C::A_BYTES, arow, brow, 0, q);
+    ktile_dma<C, true, 0>(cx, f, acc, bufs, s0, s1, rows_in, kfull, P.k, arow, brow, q);
+    // staged k-tiles in groups of NSTAGE so the buffer of each is a constant
+    for (int it = s0 + 1; it < s1; it += NS) {
+        ktile_dma<C, false, 1 % NS>(cx, f, acc, bufs, it, s1, rows_in, kfull, P.k, arow, brow, q);
+        if constexpr (NS >= 2) {
+            if (it + 1 < s1) ktile_dma<C, false, 2 % NS>(cx, f, acc, bufs, it + 1, s1, rows_in, kfull, P.k, arow, brow, q);
         }
-    } else {
-        for (int it = it0 + 1; it < it1; it += 2) {
-            ktile_dma<C, false, 1>(cx, f, acc, lds0, lds1, lds2, it, it1, rows_in, kfull, P.k, arow, brow, q);
-            if (it + 1 < it1)
-                ktile_dma<C, false, 0>(cx, f, acc, lds0, lds1, lds2, it + 1, it1, rows_in, kfull, P.k, arow, brow,
-                                       q);
+        if constexpr (NS >= 3) {
+            if (it + 2 < s1) ktile_dma<C, false, 3 % NS>(cx, f, acc, bufs, it + 2, s1, rows_in, kfull, P.k, arow, brow, q);
+        }
+        if constexpr (NS >= 4) {
+            if (it + 3 < s1) ktile_dma<C, false, 4 % NS>(cx, f, acc, bufs, it + 3, s1, rows_in, kfull, P.k, arow, brow, q);
         }
     }
 }
@@ -692,7 +716,7 @@ __device__ __forceinline__ typename C::Frag add_peers(typename C::Frag v, const 
 // loads; a barrier after the epilogue keeps the next unit's DMA away.
 template <class C>
 struct FixStage {
-    static constexpr int PH = C::SLOT_BYTES > 2 * C::STAGE ? 2 : 1;   // phases
+    static constexpr int PH = C::SLOT_BYTES > 2 * C::STAGE ? C::SLOT_BYTES / (2 * C::STAGE) : 1;   // phases
     static constexpr int VPH = C::ACC_CHUNKS / PH;                    // chunks per thread per phase
     static constexpr int H = VPH / 2;                                 // chunks per buffer
     static constexpr int ROWS_PH = C::FM / PH;                        // fragment rows per phase
@@ -1020,7 +1044,9 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     // the two k-tile buffers of the MAC loop
     __shared__ __attribute__((aligned(16))) char lds0[C::STAGE];
     __shared__ __attribute__((aligned(16))) char lds1[C::STAGE];
-    __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE == 3 ? C::STAGE : 16];
+    __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE >= 3 ? C::STAGE : 16];
+    __shared__ __attribute__((aligned(16))) char lds3[C::NSTAGE >= 4 ? C::STAGE : 16];
+    const LdsBufs bufs{lds0, lds1, lds2, lds3};
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
     int x = b;
@@ -1080,7 +1106,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         int tid = tid0;
         asm volatile("" : "+v"(tid));
         typename C::Frag acc[C::FM][C::FN];
-        mac_loop<C>(P, tm, tn, k0, k1, acc, lds0, lds1, lds2, tid);
+        mac_loop<C>(P, tm, tn, k0, k1, acc, bufs, tid);
         if (!started) {
             store_partial<C>((char *)p.partials + (int64_t)x * C::SLOT_BYTES, acc, tid);
             signal_flag(p.flags + x * FLAG_STRIDE, tid);
