@@ -114,6 +114,13 @@ struct Cfg {
     static constexpr int NSTAGE = D == Dt::F64 ? 3 : (KROW == 64 ? 4 : 2);
     static constexpr int LDS = NSTAGE * STAGE;
     static constexpr int DMA_PER_KTILE = STAGE / 4096;   // LDS-DMA loads per wave per staged k-tile
+    // k-tile instruction order pinned for the scheduler (MFMAs interleaved
+    // with the loads and fragment reads, barrier before the last k-step):
+    // measured faster for the 16-bit 256x256 tile (one workgroup, so one
+    // wave, per SIMD) and for FP8; slower for the 16-bit 128x128 tile (two
+    // workgroups per CU cover each other's stalls) and FP64, which keep the
+    // compiler's order
+    static constexpr bool ORDERED = D == Dt::F8 || (E == 2 && BM >= 256);
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
     // tile, whose transpose-read fragments leave no registers for it)
     static constexpr bool FIX_LDS = !(D == Dt::F8 && BM >= 256);
@@ -220,23 +227,30 @@ struct StageDma {
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16, o, so, 0, 0);
     }
 
-    // Issue the loads of k-tile kt into the operand stage at `lds`.
-    __device__ __forceinline__ void issue(char *lds, int kt, int K, bool interior) const {
+    // Issue the loads of k-tile kt into the operand stage at `lds`.  live
+    // false: the loads still run (out of range, depositing zeros), so the
+    // caller needs no branch around them.  interior: no row or k edge.
+    // ORDERED configurations stay branch-free (a k-tile is one basic block,
+    // whose loads the scheduler places between the MFMAs); the others take
+    // a branch to the plain interior loads.
+    __device__ __forceinline__ void issue(char *lds, int kt, int K, bool live, bool interior) const {
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
         constexpr int BLK = 4096;                       // LDS bytes between a wave's blocks
-        if (interior) {
+        if (!C::ORDERED && live && interior) {
 #pragma unroll
             for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, voff, i * ustride);
         } else if constexpr (KC) {
-            const bool kv = kt * BK + kofs < K;
+            const bool kv = live && (interior || kt * BK + kofs < K);
 #pragma unroll
-            for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, (kv && i < rows_valid) ? voff : OOB, i * ustride);
+            for (int i = 0; i < NL; ++i)
+                dma(rs, lds + lds_w + i * BLK, (kv && (interior || i < rows_valid)) ? voff : OOB, i * ustride);
         } else {
             const int k0 = kt * BK + kofs;
 #pragma unroll
             for (int i = 0; i < NL; ++i)
-                dma(rs, lds + lds_w + i * BLK, (mn_valid && k0 + i * 4 * KR < K) ? voff : OOB, i * ustride);
+                dma(rs, lds + lds_w + i * BLK, (live && (interior || (mn_valid && k0 + i * 4 * KR < K))) ? voff : OOB,
+                    i * ustride);
         }
     }
 };
@@ -266,25 +280,6 @@ struct LdsBufs {
     }
 };
 
-// Wait until at most n (< LA) staged k-tiles of this wave's loads are
-// still in flight (each staged k-tile is DPK loads).
-template <int LA, int DPK>
-__device__ __forceinline__ void wait_landed(int n) {
-    if constexpr (LA >= 3) {
-        if (n >= 2) {
-            wait_dma_but<2 * DPK>();
-            return;
-        }
-    }
-    if constexpr (LA >= 2) {
-        if (n >= 1) {
-            wait_dma_but<DPK>();
-            return;
-        }
-    }
-    wait_dma();
-}
-
 // ---------------------------------------------------------------------------
 // MFMA operand fragments
 //
@@ -302,6 +297,11 @@ struct Frag {
     static constexpr int CPM = (C::DT == Dt::F8) ? 2 : 1;          // chunks per lane per operand
     static constexpr int CHUNKS = C::KROW / 16;                     // chunks per staged LDS row
     static constexpr int NSUB = (C::DT == Dt::F64) ? CHUNKS / 4 : CHUNKS / (2 * CPM);   // k-steps per staged k-tile
+    // MFMAs and LDS fragment reads per k-step
+    static constexpr int MFMAS = C::FM * C::FN * (C::DT == Dt::F64 ? 2 : 1);
+    static constexpr int READS_PER_FRAG = C::DT == Dt::F8 ? 4 : 2;   // transpose / 8-byte reads
+    static constexpr int READS = (C::AKC ? C::FM * CPM : C::FM * READS_PER_FRAG) +
+                                 (C::BKC ? C::FN * CPM : C::FN * READS_PER_FRAG);
     u32x4 a[C::FM][CPM], b[C::FN][CPM];
 };
 
@@ -470,11 +470,59 @@ struct Ctx {
     StageDma<C, C::BN, C::BKC> sb;
 };
 
+// Instruction order of one staged k-tile, for the scheduler's group
+// barriers.  With one workgroup per CU each SIMD runs a single wave, which
+// issues in order: a burst of loads stalls the MFMAs queued behind it.  So
+// the k-tile's MFMAs go one by one, its DMA issues spread over the first
+// k-step's MFMAs (early enough that they land by the k-tile's end), and
+// each k-step's fragment reads for the next k-step spread over the first
+// half of its MFMAs (so they have landed when the next k-step starts).
+template <class C>
+__device__ __forceinline__ void order_ktile() {
+    constexpr int NSUB = Frag<C>::NSUB, MF = Frag<C>::MFMAS, RD = Frag<C>::READS;
+    constexpr int DMA = C::DMA_PER_KTILE, SPAN = MF;
+    constexpr int RSPAN = MF >= 2 ? MF / 2 : 1;     // reads go in the step's first half
+    static_for<NSUB * MF>([&](auto gg) {
+        constexpr int g = decltype(gg)::value, m = g % MF;
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                 // one MFMA
+        constexpr int nd = g < SPAN ? (g + 1) * DMA / SPAN - g * DMA / SPAN : 0;
+        if constexpr (nd > 0) __builtin_amdgcn_sched_group_barrier(0x010, nd, 0);   // DMA issues
+        constexpr int nr = m < RSPAN ? (m + 1) * RD / RSPAN - m * RD / RSPAN : 0;
+        if constexpr (nr > 0) __builtin_amdgcn_sched_group_barrier(0x100, nr, 0);   // fragment reads
+    });
+}
+
+// Wait until at most n (< LA) staged k-tiles of this wave's loads are
+// still in flight (each staged k-tile is DPK loads).
+template <int LA, int DPK>
+__device__ __forceinline__ void wait_landed(int n) {
+    if constexpr (LA >= 3) {
+        if (n >= 2) {
+            wait_dma_but<2 * DPK>();
+            return;
+        }
+    }
+    if constexpr (LA >= 2) {
+        if (n >= 1) {
+            wait_dma_but<DPK>();
+            return;
+        }
+    }
+    wait_dma();
+}
+
 // One staged k-tile.  FIRST: the segment's first, whose first k-step starts
 // the accumulators from zero.  P: which buffer holds it.  With NSTAGE
 // buffers the loads run NSTAGE - 1 staged k-tiles ahead.  The buffers are
 // distinct LDS objects, so the compiler can tell that the fragment reads of
 // one never wait for the DMA writes into another.
+//  ORDERED: one basic block -- loads past the segment's end are issued out
+//  of range (they deposit zeros into a free buffer), the barrier comes
+//  before the last k-step's MFMAs, which then cover the first fragment reads
+//  of the next k-tile (read unconditionally: after the segment's last k-tile
+//  they are dead), and order_ktile pins the interleaving.
+//  Otherwise: loads and the next k-tile's first reads sit behind branches
+//  and the barrier ends the k-tile.
 template <class C, bool FIRST, int P>
 __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename C::Frag (&acc)[C::FM][C::FN],
                                           const LdsBufs &bufs, int it, int it1, bool rows_in, int kfull, int K,
@@ -482,25 +530,41 @@ __device__ __forceinline__ void ktile_dma(Ctx<C> &cx, Frag<C> (&f)[2], typename 
     constexpr int NSUB = Frag<C>::NSUB;
     constexpr int NS = C::NSTAGE, LA = NS - 1;
     const char *st = bufs.template get<P>();
-    char *nx = bufs.template get<(P + 1) % NS>();
+    const char *nx = bufs.template get<(P + 1) % NS>();
     char *ld = bufs.template get<(P + LA) % NS>();
-    const bool more = it + 1 < it1;
-    if (it + LA < it1) {
-        const bool in = rows_in && it + LA < kfull;
-        cx.sa.issue(ld, it + LA, K, in);
-        cx.sb.issue(ld + C::A_BYTES, it + LA, K, in);
+    const bool live = it + LA < it1;
+    const bool in = rows_in && it + LA < kfull;
+    if constexpr (C::ORDERED) {
+        cx.sa.issue(ld, it + LA, K, live, in);
+        cx.sb.issue(ld + C::A_BYTES, it + LA, K, live, in);
+        static_for<NSUB - 1>([&](auto kk) {
+            constexpr int ks = decltype(kk)::value;
+            read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
+            mfma_step<C, FIRST && ks == 0>(acc, f[ks & 1]);
+        });
+        // staged k-tile it+1 must have landed; the LA-1 after it may still
+        // be in flight (every k-tile issues the same number of loads)
+        wait_dma_but<(LA - 1) * C::DMA_PER_KTILE>();
+        __syncthreads();
+        read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
+        mfma_step<C, false>(acc, f[(NSUB - 1) & 1]);
+        order_ktile<C>();
+    } else {
+        if (live) {
+            cx.sa.issue(ld, it + LA, K, true, in);
+            cx.sb.issue(ld + C::A_BYTES, it + LA, K, true, in);
+        }
+        static_for<NSUB>([&](auto kk) {
+            constexpr int ks = decltype(kk)::value;
+            if constexpr (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
+            mfma_step<C, FIRST && ks == 0>(acc, f[ks & 1]);
+        });
+        // staged k-tile it+1 must have landed; newer ones may stay in flight
+        const int newer = it1 - 1 - (it + 1) < LA - 1 ? it1 - 1 - (it + 1) : LA - 1;
+        wait_landed<LA, C::DMA_PER_KTILE>(newer);
+        __syncthreads();
+        if (it + 1 < it1) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
     }
-#pragma unroll
-    for (int ks = 0; ks < NSUB; ++ks) {
-        if (ks + 1 < NSUB) read_frags<C>(f[(ks + 1) & 1], st, st + C::A_BYTES, arow, brow, ks + 1, q);
-        if (FIRST && ks == 0) mfma_step<C, true>(acc, f[0]);
-        else mfma_step<C, false>(acc, f[ks & 1]);
-    }
-    // staged k-tile it+1 must have landed; newer ones may stay in flight
-    const int newer = it1 - 1 - (it + 1) < LA - 1 ? it1 - 1 - (it + 1) : LA - 1;
-    wait_landed<LA, C::DMA_PER_KTILE>(newer);
-    __syncthreads();
-    if (more) read_frags<C>(f[0], nx, nx + C::A_BYTES, arow, brow, 0, q);
 }
 
 template <class C>
@@ -536,15 +600,18 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
     const int s0 = it0 * C::SUB, s1 = it1 * C::SUB;
     const int kfull = P.k / C::BKS;                // staged k-tiles with no k edge
     constexpr int NS = C::NSTAGE, LA = NS - 1;
+    // ORDERED issues every prologue load (out of range past the segment's
+    // end), so the loads in flight are always LA staged k-tiles
     static_for<LA>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
-        if (s0 + j < s1) {
-            const bool in = rows_in && s0 + j < kfull;
-            cx.sa.issue(bufs.template get<j>(), s0 + j, P.k, in);
-            cx.sb.issue(bufs.template get<j>() + C::A_BYTES, s0 + j, P.k, in);
+        const bool in = rows_in && s0 + j < kfull;
+        if (C::ORDERED || s0 + j < s1) {
+            cx.sa.issue(bufs.template get<j>(), s0 + j, P.k, s0 + j < s1, in);
+            cx.sb.issue(bufs.template get<j>() + C::A_BYTES, s0 + j, P.k, s0 + j < s1, in);
         }
     });
-    wait_landed<LA, C::DMA_PER_KTILE>(s1 - 1 - s0 < LA - 1 ? s1 - 1 - s0 : LA - 1);
+    if constexpr (C::ORDERED) wait_dma_but<(LA - 1) * C::DMA_PER_KTILE>();
+    else wait_landed<LA, C::DMA_PER_KTILE>(s1 - 1 - s0 < LA - 1 ? s1 - 1 - s0 : LA - 1);
     __syncthreads();
     Frag<C> f[2];
     read_frags<C>(f[0], bufs.b0, bufs.b0 + C::A_BYTES, arow, brow, 0, q);
