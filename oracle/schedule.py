@@ -130,12 +130,13 @@ def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
         return Plan(0, 0, 0, False, SCHED_DP if sched == SCHED_AUTO else sched, 0, [])
     if sched == SCHED_AUTO:
         # the library's automatic choice (a measured policy, not the paper's):
-        # basic Stream-K while the tiles cannot give every CU a workgroup,
-        # data-parallel tiles otherwise; FP64 takes the two-tile hybrid
+        # basic Stream-K while the tiles give no CU more than one workgroup
+        # (t <= CUs), data-parallel tiles otherwise; FP64 takes the two-tile
+        # hybrid
         if auto_two_tile:
             sched = SCHED_2T
         else:
-            sched = SCHED_SK if t < cus else SCHED_DP
+            sched = SCHED_SK if t <= cus else SCHED_DP
     if sched == SCHED_DP:
         return Plan(t, 0, 0, True, SCHED_DP, t, list(range(t)))
     if sched == SCHED_SK:

@@ -338,8 +338,10 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
     }
     if (sched == SK_SCHED_AUTO) {
-        // Measured on MI355X: Stream-K pays off while the tiles cannot give
-        // every CU a workgroup (t < CUs); from there on, one data-parallel
+        // Measured on MI355X: Stream-K pays off while the tiles give no CU
+        // more than one workgroup (t <= CUs: a lone workgroup leaves its
+        // CU's second slot idle, which a Stream-K split fills -- 2048^2 x
+        // 8192 BF16: DP 634, SK 889 TFLOP/s); from there on, one data-parallel
         // workgroup per tile is at least as fast as the hybrids -- with two
         // or more workgroups resident per CU the last partial wave costs
         // little, while a Stream-K region loses the k-aligned L2 reuse of
@@ -349,7 +351,7 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         // size (FP64 sweep: basic SK 47.5, two-tile hybrid 47.8, the rule
         // above 43.7, DP 30.6 TFLOP/s): the paper's two-tile hybrid.
         if (c.key.ab_type == SK_F64) sched = SK_SCHED_2TILE_SK_DP;
-        else sched = t < cus ? SK_SCHED_SK : SK_SCHED_DP;
+        else sched = t <= cus ? SK_SCHED_SK : SK_SCHED_DP;
     }
     if (sched == SK_SCHED_DP) {
         pl->sched = SK_SCHED_DP;

@@ -195,12 +195,13 @@ def test_auto_tile_and_schedule_policy():
     assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 16)
     st, pl = S.sk_plan(desc(m=8192, n=8192, k=512, ab_type="f8e4m3", c_type="bf16", a_scale=0.5, b_scale=0.5), cfg)
     assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 128)
-    # AUTO: basic Stream-K while t < CUs (= wg_slots / LDS-bound workgroups per CU), else DP
+    # AUTO: basic Stream-K while t <= CUs (= wg_slots / LDS-bound workgroups per CU), else DP
     blk = (128, 128, 64)
     cus = 512 // O.lds_wgs_per_cu(128, 128)
     assert cus == 256
     for (m, n, want) in ((1024, 1024, S.SK_SCHED_SK), (2048, 2048 - 128, S.SK_SCHED_SK),
-                         (2048, 2048, S.SK_SCHED_DP), (4096, 4096, S.SK_SCHED_DP)):
+                         (2048, 2048, S.SK_SCHED_SK), (2048, 2048 + 128, S.SK_SCHED_DP),
+                         (4096, 4096, S.SK_SCHED_DP)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="f16", c_type="f32"),
                            S.make_config(blk=blk, wg_slots=512))
         assert st == S.SK_OK and pl.sched == want, (m, n, pl.sched)
