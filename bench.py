@@ -517,7 +517,7 @@ def main():
         "config": {"workload": "geometry sweep: 2048 GEMMs, m,n,k log-uniform in [128,8192] rounded "
                                "to multiples of 8 (seed 1); FP16 inputs U[-1,1], FP32 accumulate "
                                "and output; alpha=1, beta=0; row-major; library default configuration "
-                               "(basic Stream-K while tiles < CUs, else data-parallel; 128x128 tiles "
+                               "(basic Stream-K while tiles <= CUs, else data-parallel; 128x128 tiles "
                                "unless 8 full waves)",
                    "problems": len(shapes), "flops_per_step": total_flops,
                    "tiles": tiles, "schedules": kinds},

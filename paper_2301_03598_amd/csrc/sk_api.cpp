@@ -54,8 +54,8 @@ struct Model {
 Model default_model(int ab, int bm) {
     switch (ab) {
     case SK_F64: return bm >= 128 ? Model{13.8, 0.0, 2.22, 5.56} : Model{8.9, 0.0, 0.82, 1.69};
-    case SK_F8_E4M3: return bm >= 256 ? Model{49.9, 0.0, 5.40, 6.91} : Model{0.0, 9.19, 1.49, 1.82};
-    default: return bm >= 256 ? Model{17.3, 0.4, 1.52, 6.19} : Model{0.0, 12.4, 0.74, 1.05};
+    case SK_F8_E4M3: return bm >= 256 ? Model{26.8, 0.61, 1.62, 6.78} : Model{0.0, 14.4, 0.83, 1.06};
+    default: return bm >= 256 ? Model{23.6, 0.0, 1.43, 5.99} : Model{0.0, 12.4, 0.74, 1.05};
     }
 }
 
