@@ -48,7 +48,8 @@ typedef enum { SK_F64 = 0, SK_F32 = 1, SK_F16 = 2, SK_BF16 = 3, SK_F8_E4M3 = 4 }
 
 /* Work decompositions (paper sections 3.2, 4 and 5.2). */
 typedef enum {
-    SK_SCHED_AUTO = 0,          /* library default, measured on MI355X: basic SK while t <= CUs, else DP;
+    SK_SCHED_AUTO = 0,          /* library default, measured on MI355X: basic SK while t <= CUs, else DP
+                                   (a single GEMM whose model grid is one workgroup per tile: DP);
                                    F64: the two-tile SK + DP hybrid */
     SK_SCHED_DP = 1,            /* data-parallel: one workgroup per output tile (Algorithm 2) */
     SK_SCHED_SK = 2,            /* basic Stream-K over all tiles (Algorithm 5), g from the model */

@@ -121,10 +121,11 @@ def choose_grid(T: int, I: int, p: int, consts: Tuple[float, float, float, float
 
 def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
               grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0,
-              auto_two_tile: bool = False) -> Plan:
+              auto_two_tile: bool = False, single: bool = True) -> Plan:
     """``T_of_region(tb, te)`` returns the iteration count of tiles [tb, te).
     ``cus``: the CU count that the automatic schedule compares t with;
-    ``auto_two_tile``: the automatic schedule is the two-tile hybrid (FP64)."""
+    ``auto_two_tile``: the automatic schedule is the two-tile hybrid (FP64);
+    ``single``: the call holds one problem (not a grouped call of several)."""
     t = tiles
     if t == 0:
         return Plan(0, 0, 0, False, SCHED_DP if sched == SCHED_AUTO else sched, 0, [])
@@ -135,8 +136,15 @@ def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
         # hybrid
         if auto_two_tile:
             sched = SCHED_2T
+        elif t <= cus:
+            sched = SCHED_SK
+            # one problem whose model grid is one workgroup per tile: that is
+            # the data-parallel schedule, and the library runs it as such
+            if single and grid <= 0 and min(choose_grid(T_of_region(0, t), I_max, p, consts),
+                                           T_of_region(0, t)) == t:
+                sched = SCHED_DP
         else:
-            sched = SCHED_SK if t <= cus else SCHED_DP
+            sched = SCHED_DP
     if sched == SCHED_DP:
         return Plan(t, 0, 0, True, SCHED_DP, t, list(range(t)))
     if sched == SCHED_SK:
@@ -243,7 +251,8 @@ def plan_problems(probs: Problems, p: int, sched: int, grid: int = 0,
     # the model's per-tile iteration count is that of the deepest tile that
     # exists: a problem with no output tiles has no MAC-loop iterations
     depth = max((I for t, I in zip(probs.tp, probs.Ip) if t > 0), default=0)
-    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus, auto_two_tile)
+    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus, auto_two_tile,
+                     single=len(probs.tp) == 1)
 
 
 def segments(probs: Problems, plan: Plan) -> List[List[Segment]]:

@@ -351,7 +351,16 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         // size (FP64 sweep: basic SK 47.5, two-tile hybrid 47.8, the rule
         // above 43.7, DP 30.6 TFLOP/s): the paper's two-tile hybrid.
         if (c.key.ab_type == SK_F64) sched = SK_SCHED_2TILE_SK_DP;
-        else sched = t <= cus ? SK_SCHED_SK : SK_SCHED_DP;
+        else if (t <= cus) {
+            sched = SK_SCHED_SK;
+            // a model grid of exactly one workgroup per tile (one problem)
+            // is the data-parallel schedule: run the data-parallel kernel
+            if (user_grid == 0 && c.probs.size() == 1 &&
+                std::min<int64_t>(model_grid(c.iters, c.imax, p, mc), c.iters) == t)
+                sched = SK_SCHED_DP;
+        } else {
+            sched = SK_SCHED_DP;
+        }
     }
     if (sched == SK_SCHED_DP) {
         pl->sched = SK_SCHED_DP;

@@ -199,9 +199,11 @@ def test_auto_tile_and_schedule_policy():
     blk = (128, 128, 64)
     cus = 512 // O.lds_wgs_per_cu(128, 128)
     assert cus == 256
-    for (m, n, want) in ((1024, 1024, S.SK_SCHED_SK), (2048, 2048 - 128, S.SK_SCHED_SK),
-                         (2048, 2048, S.SK_SCHED_SK), (2048, 2048 + 128, S.SK_SCHED_DP),
-                         (4096, 4096, S.SK_SCHED_DP)):
-        st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="f16", c_type="f32"),
+    for (m, n, k, want) in ((1024, 1024, 8192, S.SK_SCHED_SK), (2048, 2048 - 128, 8192, S.SK_SCHED_SK),
+                            (2048, 2048, 8192, S.SK_SCHED_SK), (2048, 2048 + 128, 8192, S.SK_SCHED_DP),
+                            (4096, 4096, 8192, S.SK_SCHED_DP),
+                            # shallow k: the model grid is one workgroup per tile, i.e. DP
+                            (1024, 1024, 512, S.SK_SCHED_DP), (2048, 2048, 512, S.SK_SCHED_DP)):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type="f16", c_type="f32"),
                            S.make_config(blk=blk, wg_slots=512))
-        assert st == S.SK_OK and pl.sched == want, (m, n, pl.sched)
+        assert st == S.SK_OK and pl.sched == want, (m, n, k, pl.sched)
