@@ -984,8 +984,8 @@ __device__ __forceinline__ void store_partial(char *slot, const typename C::Frag
 // ---------------------------------------------------------------------------
 // flags.  Partial tiles and flags are all device-coherent accesses (SC1):
 // the producer waits until its partial stores have completed, then one
-// thread raises the flag; the owner polls the flag and issues its partial
-// loads only after it has seen it.  Program order plus completion waits
+// thread raises the flag; the owner polls its peers' flags (one lane per
+// peer) and issues its partial loads only after it has seen all of them.  Program order plus completion waits
 // order the accesses; no cache-wide fence is needed.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void signal_flag(int32_t *flag, int tid) {
@@ -994,20 +994,34 @@ __device__ __forceinline__ void signal_flag(int32_t *flag, int tid) {
     if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void wait_flag(int32_t *flag, int32_t *err, int limit, int tid) {
-    if (tid == 0) {
-        int n = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++n >= limit) {             // bounded: give up, report, never hang
-                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
+// Wait until the flags of peers first..last are all raised, then clear them.
+// Wave 0 polls up to 64 peers per round, one per lane, so a round costs one
+// load latency however many peers there are; the other waves wait at the
+// barrier.  Bounded: after `limit` polls the error word is set and the wait
+// ends (the partial tiles of a peer that never arrived are then garbage and
+// the call reports SK_ERR_TIMEOUT).
+__device__ __forceinline__ void wait_flags(int32_t *flags, int first, int last, int32_t *err, int limit, int tid) {
+    if (tid < 64) {
+        for (int base = first; base <= last; base += 64) {
+            const int peer = base + tid;
+            const bool mine = peer <= last;
+            int32_t *f = flags + (int64_t)(mine ? peer : first) * FLAG_STRIDE;
+            bool seen = !mine;
+            int n = 0;
+            while (true) {
+                if (!seen) seen = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (__all(seen)) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++n >= limit) {         // bounded: give up, report, never hang
+                    if (tid == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
             }
+            if (mine) __hip_atomic_store(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // consumed
         }
-        __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // consumed
     }
     // the workgroup barrier (with its compiler-level ordering) keeps every
-    // wave's partial loads behind the observed flag
+    // wave's partial loads behind the observed flags
     __syncthreads();
 }
 
@@ -1184,8 +1198,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         if (!ended) {
             const int li = t1 - 1;
             last = li < rq ? li / (q + 1) : r + (li - rq) / q;
-            for (int peer = x + 1; peer <= last; ++peer)
-                wait_flag(p.flags + peer * FLAG_STRIDE, p.err, p.spin_limit, tid);
+            wait_flags(p.flags, x + 1, last, p.err, p.spin_limit, tid);
         }
         // peers' partial tiles are added in ascending slot order inside the
         // epilogue, fragment by fragment
