@@ -53,9 +53,9 @@ struct Model {
 
 Model default_model(int ab, int bm) {
     switch (ab) {
-    case SK_F64: return bm >= 128 ? Model{13.8, 0.0, 2.22, 5.56} : Model{8.9, 0.0, 0.82, 1.69};
-    case SK_F8_E4M3: return bm >= 256 ? Model{26.8, 0.61, 1.62, 6.78} : Model{0.0, 14.4, 0.83, 1.06};
-    default: return bm >= 256 ? Model{23.6, 0.0, 1.43, 5.99} : Model{0.0, 12.4, 0.74, 1.05};
+    case SK_F64: return bm >= 128 ? Model{15.6, 4.41, 2.03, 1.65} : Model{6.22, 2.22, 0.73, 0.43};
+    case SK_F8_E4M3: return bm >= 256 ? Model{27.8, 0.0, 1.62, 6.39} : Model{0.0, 13.2, 0.82, 0.64};
+    default: return bm >= 256 ? Model{25.2, 0.0, 1.41, 5.47} : Model{0.0, 11.2, 0.73, 0.64};
     }
 }
 
