@@ -629,6 +629,11 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
             if (it + 3 < s1) ktile_dma<C, false, 4 % NS>(cx, f, acc, bufs, it + 3, s1, rows_in, kfull, P.k, arow, brow, q);
         }
     }
+    // ORDERED with more than two buffers would leave the out-of-range loads
+    // past the segment's end in flight; the epilogue's staging reuses the
+    // buffers, so they must land first (the other path waits for every load
+    // in its last k-tile)
+    if constexpr (C::ORDERED && LA > 1) wait_dma();
 }
 
 // ---------------------------------------------------------------------------
