@@ -504,7 +504,10 @@ def main():
         ext["grouped"] = grouped_leg()
         log("grouped:", ext["grouped"])
         ext["serving"] = serving_leg()
-        log("serving:", ext["serving"])
+        # the same stream at half the rate: below what the GPU sustains on
+        # this mix, so the latencies are those of an unsaturated server
+        ext["serving_half_rate"] = serving_leg(rate=10000.0)
+        log("serving:", ext["serving"], "half rate:", ext["serving_half_rate"])
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     if cpu:
         log("cpu baseline:", cpu)
