@@ -304,6 +304,44 @@ def extended():
     return out
 
 
+def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20) -> dict:
+    """One precision-set style GEMM (N(0,1) operands from seed 2, BF16 output
+    for 16-bit and FP8 inputs, FP64 for FP64), default configuration: 3
+    warm-up launches, then `reps` timed back to back."""
+    import torch
+    import workloads as W
+    from paper_2301_03598_amd import runtime as R
+    from paper_2301_03598_amd import streamk as S
+    ct = "f64" if ab == "f64" else "bf16"
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    A = torch.empty(m * k, dtype=W.torch_dtype(ab), device="cuda")
+    B = torch.empty(k * n, dtype=W.torch_dtype(ab), device="cuda")
+    W.device_fill_(A, "normal", gen)
+    W.device_fill_(B, "normal", gen)
+    C = torch.empty(m * n, dtype=W.torch_dtype(ct), device="cuda")
+    cfg = S.make_config()
+    d = S.make_desc(m, n, k, A, B, C, ab_type=ab, c_type=ct, a_scale=1.0, b_scale=1.0)
+    st, pl = S.sk_plan(d, cfg)
+    S.check(st, "sk_plan")
+    ws = R.Workspace("cuda", pl.workspace_bytes)
+    s = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        S.check(S.sk_gemm(d, cfg, ws.ptr, ws.nbytes, s), "sk_gemm")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        S.sk_gemm(d, cfg, ws.ptr, ws.nbytes, s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+    return {"gemm": f"{m}x{n}x{k}", "ab": ab, "c": ct, "reps": reps, "ms": round(ms, 4),
+            "tflops": round(tf, 1), "pct_peak": round(100 * tf / PEAK_TFLOPS[ab], 2),
+            "sched": S.SCHED_NAME.get(pl.sched, pl.sched), "grid": pl.grid,
+            "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}"}
+
+
 def grouped_leg(tune: bool = True):
     """512 BF16 GEMMs (seed 3): one grouped persistent launch captured in a
     HIP graph and replayed, against 512 separate sk_gemm launches; the
@@ -404,9 +442,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--extended", action="store_true")
+    ap.add_argument("--gemm", nargs=4, metavar=("M", "N", "K", "AB"),
+                    help="time one GEMM of the given shape and input dtype (default configuration) "
+                         "and print its JSON; for profiling a single kernel")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.gemm:
+        import torch
+        from paper_2301_03598_amd import streamk as S
+        S.lib()
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        m, n, k = (int(v) for v in args.gemm[:3])
+        print(json.dumps(one_gemm(m, n, k, args.gemm[3])), flush=True)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
