@@ -207,3 +207,11 @@ def test_auto_tile_and_schedule_policy():
         st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type="f16", c_type="f32"),
                            S.make_config(blk=blk, wg_slots=512))
         assert st == S.SK_OK and pl.sched == want, (m, n, k, pl.sched)
+    # the one-workgroup-per-tile shortcut is for single GEMMs: a grouped call
+    # of the same shallow problems keeps basic Stream-K over their union
+    d1 = desc(m=1024, n=1024, k=512, ab_type="f16", c_type="f32")
+    st, pl = S.sk_plan([d1, d1], S.make_config(blk=blk, wg_slots=512))
+    assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK and pl.tiles == 128
+    # an explicit grid is honoured as Stream-K even when it equals t
+    st, pl = S.sk_plan(d1, S.make_config(blk=blk, wg_slots=512, grid=64))
+    assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK and pl.grid == 64
