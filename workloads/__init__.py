@@ -98,7 +98,7 @@ class Operand:
 
 
 def fp8_absmax_scale(x: np.ndarray) -> float:
-    """Per-tensor scale s = absmax / 448, held in FP32 (spec recipe)."""
+    """Per-tensor scale s = absmax / 448, held in FP32 (the precision set's FP8 recipe)."""
     amax = float(np.max(np.abs(x))) if x.size else 0.0
     s = np.float32(amax / FP8_E4M3_MAX) if amax > 0 else np.float32(1.0)
     return float(s)
