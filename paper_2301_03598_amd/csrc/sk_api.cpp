@@ -20,14 +20,15 @@ struct TileDef {
 
 // Built tiles per input dtype; the first entry is the default.  The paper
 // keeps one tile per precision, the smallest that reaches its near-peak rate
-// on very large problems (section 5.1).  For FP16/BF16 the automatic choice
-// takes the second (128x128) tile unless the problem fills at least
-// kBigTileWaves full waves of it (in build_call).  FP8 defaults to 128x128
-// outright: with LDS-DMA staging it is faster even on 8192^3 (1894 vs 1552
-// TFLOP/s), where the 256x256 tile's registers run out.
+// on very large problems (section 5.1).  For FP16/BF16 and FP8 the
+// automatic choice takes the second (128x128) tile unless the problem fills
+// at least kBigTileWaves full waves of it (in build_call): the 256x256 tile
+// moves half the operand bytes per flop, which wins once quantisation no
+// longer matters (FP8 8192^3: 1994 vs 1631 TFLOP/s row/row, 2300 vs 2086
+// row/col), while the 128x128 tile fills the machine on smaller problems.
 const TileDef kF64Tiles[] = {{128, 128, 16}, {64, 64, 16}};
 const TileDef k16Tiles[] = {{256, 256, 64}, {128, 128, 64}};
-const TileDef kF8Tiles[] = {{128, 128, 128}, {256, 256, 128}};   // 128x128 default (measured)
+const TileDef kF8Tiles[] = {{256, 256, 128}, {128, 128, 128}};
 
 const TileDef *tiles_for(int ab, int *n) {
     *n = 2;
@@ -259,7 +260,7 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
     sk_status_t s = resolve_tile(d[0].ab_type, cfg, &c->tile);
     if (s != SK_OK) return s;
     const bool tile_given = cfg && (cfg->blk_m != 0 || cfg->blk_n != 0 || cfg->blk_k != 0);
-    if (!tile_given && (d[0].ab_type == SK_F16 || d[0].ab_type == SK_BF16)) {
+    if (!tile_given && (d[0].ab_type == SK_F16 || d[0].ab_type == SK_BF16 || d[0].ab_type == SK_F8_E4M3)) {
         // the 128x128 tile unless there are kBigTileWaves full waves of it
         int n = 0;
         const TileDef small = tiles_for(d[0].ab_type, &n)[1];

@@ -30,7 +30,7 @@ from . import streamk as S
 TILES = {"f64": [(128, 128, 16), (64, 64, 16)],
          "f16": [(256, 256, 64), (128, 128, 64)],
          "bf16": [(256, 256, 64), (128, 128, 64)],
-         "f8e4m3": [(128, 128, 128), (256, 256, 128)]}
+         "f8e4m3": [(256, 256, 128), (128, 128, 128)]}
 CTYPE = {"f64": "f64", "f16": "f32", "bf16": "f32", "f8e4m3": "f32"}
 
 

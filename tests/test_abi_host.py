@@ -190,11 +190,13 @@ def test_auto_tile_and_schedule_policy():
     for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 128), (4096, 4096, 128), (256, 256, 128)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="bf16", c_type="f32"), cfg)
         assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, pl.blk_m)
-    # other dtypes keep their default tile (FP64 128x128x16, FP8 128x128x128)
+    # FP8 follows the same rule (t >= 8 p of its 128x128x128 tile -> 256x256x128)
+    for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 128), (256, 256, 128)):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="f8e4m3", c_type="bf16", a_scale=0.5, b_scale=0.5), cfg)
+        assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (blk_m, 128), (m, n, pl.blk_m)
+    # FP64 keeps its default tile (128x128x16)
     st, pl = S.sk_plan(desc(m=256, n=256, k=512, ab_type="f64", c_type="f64"), cfg)
     assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 16)
-    st, pl = S.sk_plan(desc(m=8192, n=8192, k=512, ab_type="f8e4m3", c_type="bf16", a_scale=0.5, b_scale=0.5), cfg)
-    assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 128)
     # AUTO: basic Stream-K while t <= CUs (= wg_slots / LDS-bound workgroups per CU), else DP
     blk = (128, 128, 64)
     cus = 512 // O.lds_wgs_per_cu(128, 128)
