@@ -40,7 +40,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 ROLE_DP, ROLE_FULL, ROLE_OWNER, ROLE_PRODUCER = 0, 1, 2, 3
 ROLE_NAMES = {ROLE_DP: "dp", ROLE_FULL: "full", ROLE_OWNER: "owner", ROLE_PRODUCER: "producer"}
 
-SCHED_AUTO, SCHED_DP, SCHED_SK, SCHED_DP1, SCHED_2T = 0, 1, 2, 3, 4
+SCHED_DP, SCHED_SK, SCHED_DP1, SCHED_2T = 1, 2, 3, 4
 
 
 def cdiv(a: int, b: int) -> int:
@@ -120,31 +120,18 @@ def choose_grid(T: int, I: int, p: int, consts: Tuple[float, float, float, float
 
 
 def make_plan(tiles: int, T_of_region, I_max: int, p: int, sched: int,
-              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0,
-              auto_two_tile: bool = False, single: bool = True) -> Plan:
-    """``T_of_region(tb, te)`` returns the iteration count of tiles [tb, te).
-    ``cus``: the CU count that the automatic schedule compares t with;
-    ``auto_two_tile``: the automatic schedule is the two-tile hybrid (FP64);
-    ``single``: the call holds one problem (not a grouped call of several)."""
+              grid: int = 0, consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2) -> Plan:
+    """The plan of one of the paper's four schedules: data-parallel
+    (Algorithm 2), basic Stream-K (Algorithm 5, appendix A.1 grid) and the
+    two hybrids of section 5.2.  ``T_of_region(tb, te)`` returns the
+    iteration count of tiles [tb, te).  A library's own automatic choice among
+    them is not a passage of the paper, so it has no oracle: asking for it
+    raises."""
+    if sched not in (SCHED_DP, SCHED_SK, SCHED_DP1, SCHED_2T):
+        raise ValueError(f"schedule {sched} is not one of the paper's (DP, SK, DP+1-tile SK, 2-tile SK+DP)")
     t = tiles
     if t == 0:
-        return Plan(0, 0, 0, False, SCHED_DP if sched == SCHED_AUTO else sched, 0, [])
-    if sched == SCHED_AUTO:
-        # the library's automatic choice (a measured policy, not the paper's):
-        # basic Stream-K while the tiles give no CU more than one workgroup
-        # (t <= CUs), data-parallel tiles otherwise; FP64 takes the two-tile
-        # hybrid
-        if auto_two_tile:
-            sched = SCHED_2T
-        elif t <= cus:
-            sched = SCHED_SK
-            # one problem whose model grid is one workgroup per tile: that is
-            # the data-parallel schedule, and the library runs it as such
-            if single and grid <= 0 and min(choose_grid(T_of_region(0, t), I_max, p, consts),
-                                           T_of_region(0, t)) == t:
-                sched = SCHED_DP
-        else:
-            sched = SCHED_DP
+        return Plan(0, 0, 0, False, sched, 0, [])
     if sched == SCHED_DP:
         return Plan(t, 0, 0, True, SCHED_DP, t, list(range(t)))
     if sched == SCHED_SK:
@@ -239,20 +226,12 @@ class Problems:
         return self.tile_iter_begin(te - 1) + self.iters_of_tile(te - 1) - self.tile_iter_begin(tb)
 
 
-def lds_wgs_per_cu(bm: int, bn: int) -> int:
-    """Workgroups of a tile's kernel that fit one CU by LDS alone: two k-tile
-    buffers of (BM + BN) 128-byte rows in 160 KiB."""
-    return max(1, (160 * 1024) // (2 * (bm + bn) * 128))
-
-
 def plan_problems(probs: Problems, p: int, sched: int, grid: int = 0,
-                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2, cus: int = 0,
-                  auto_two_tile: bool = False) -> Plan:
+                  consts=(0.0, 10.0, 1.0, 8.5), threshold: int = 2) -> Plan:
     # the model's per-tile iteration count is that of the deepest tile that
     # exists: a problem with no output tiles has no MAC-loop iterations
     depth = max((I for t, I in zip(probs.tp, probs.Ip) if t > 0), default=0)
-    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold, cus, auto_two_tile,
-                     single=len(probs.tp) == 1)
+    return make_plan(probs.tiles, probs.region_iters, depth, p, sched, grid, consts, threshold)
 
 
 def segments(probs: Problems, plan: Plan) -> List[List[Segment]]:
