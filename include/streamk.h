@@ -103,8 +103,8 @@ typedef struct {
  *                   by the tile's workgroups per CU by LDS (160 KiB / (2 (BM +
  *                   BN) 128 B)) when wg_slots is given.
  *  grid             g, the number of persistent workgroups (SK schedules).
- *                   Must not exceed wg_slots: a fixup owner waits for
- *                   higher-numbered workgroups, so all g must be co-resident.
+ *                   Must not exceed wg_slots (a fixup waits for other
+ *                   workgroups, so all g must be co-resident) nor SK_MAX_GRID.
  *  wg_slots         p, resident workgroup slots (CUs x workgroups per CU for
  *                   the chosen kernel); 0 = queried from the current device.
  *  sk_threshold_waves  full waves w at and above which AUTO / 2TILE use the
@@ -115,11 +115,22 @@ typedef struct {
  *  trace            optional device buffer receiving one record per executed
  *                   segment (for schedule verification); trace[0] is an
  *                   int32 record counter the caller zeroes, records of 8
- *                   int32 {wg, seq, tile, k_begin, k_end, role, last_peer, 0}
+ *                   int32 {wg, seq, tile, k_begin, k_end, role, last_peer, x}
  *                   start at trace[8].  Records beyond trace_capacity are
  *                   dropped (the counter still counts them).
  *                   role: 0 DP tile, 1 whole tile in one SK segment,
- *                   2 owner (adds peers' partials), 3 producer (stores one).
+ *                   2 owner (its tile's later contributors end at last_peer),
+ *                   3 producer (stores one partial tile), 4 slice reduction
+ *                   of the spread fixup (k_begin/k_end: the 16-byte chunk
+ *                   range of the tile's partial tiles it reduced; x: the
+ *                   tile's first contributor; last_peer: its last).
+ *  wait_limit_us    bound of one fixup wait in microseconds of real time;
+ *                   0 = 2 s.  Negative: a wait gives up at once (testing
+ *                   only: a call with any split tile then reports
+ *                   SK_ERR_TIMEOUT and its results are undefined).
+ *  fixup            SK_FIXUP_*: how split tiles are reconciled.
+ *  model_bw         bytes per microsecond of the memory term of the grid
+ *                   model (spread fixup); 0 = the library's constant.
  */
 typedef struct {
     int32_t sched;
@@ -131,10 +142,27 @@ typedef struct {
     double model_a, model_b, model_c, model_d;
     int32_t *trace;
     int64_t trace_capacity;
+    int32_t wait_limit_us;
+    int32_t fixup;
+    double model_bw;
 } sk_config_t;
 
 #define SK_FLAG_NO_XCD_REMAP 0x1     /* keep logical workgroup id == hardware id */
 #define SK_FLAG_ROW_MAJOR_TILES 0x2  /* tile t -> (t / tiles_n, t % tiles_n) instead of banded order */
+
+/* Largest persistent grid, and the most peers one tile's owner may wait on
+ * (plans beyond it are rejected with SK_ERR_UNSUPPORTED, or avoided when the
+ * library picks the grid). */
+#define SK_MAX_GRID 1024
+#define SK_MAX_PEERS 64
+
+/* Fixup of a tile split over workgroups f..l (f ran the tile's first
+ * iteration).  SERIAL is Algorithm 5: f's successors store partial tiles and
+ * f adds them, in ascending order, before writing the tile.  SPREAD: every
+ * contributor stores its partial tile and then reduces 1/(l-f+1) of the tile
+ * over all of them, in the same ascending order, so both give identical
+ * bits.  AUTO (0): SPREAD when some owner has at least two peers. */
+typedef enum { SK_FIXUP_AUTO = 0, SK_FIXUP_SERIAL = 1, SK_FIXUP_SPREAD = 2 } sk_fixup_t;
 
 /* The resolved launch plan of a call (host only; no device access when
  * cfg->wg_slots > 0). */
@@ -151,6 +179,8 @@ typedef struct {
     int64_t sk_iter_begin, sk_iters;      /* the same region in iterations */
     int64_t dp_tiles;         /* tiles outside the SK region */
     uint64_t workspace_bytes;
+    int32_t fixup;            /* resolved sk_fixup_t (never AUTO) */
+    int32_t max_peers;        /* largest peer count of any tile's owner */
 } sk_plan_t;
 
 /* Plan the call without launching it.  d points to `count` descriptors

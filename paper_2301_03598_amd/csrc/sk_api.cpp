@@ -47,12 +47,21 @@ const TileDef *tiles_for(int ab, int *n) {
 // MAC-loop iteration, d reading and adding one peer's partial tile.  As the
 // paper prescribes, they were measured once on the target (MI355X, from
 // basic Stream-K timings over a range of grid sizes, least-squares fit) and
-// are compiled in; only their ratios matter to the argmin over g.
+// are compiled in; only their ratios matter to the argmin over g.  The
+// spread fixup has its own set: each contributor reads one tile's worth of
+// partials whatever the peer count, so its d is small.
 struct Model {
     double a, b, c, d;
 };
 
-Model default_model(int ab, int bm) {
+Model default_model(int ab, int bm, bool spread) {
+    if (spread) {
+        switch (ab) {
+        case SK_F64: return bm >= 128 ? Model{15.6, 6.0, 2.03, 0.1} : Model{6.22, 2.6, 0.73, 0.05};
+        case SK_F8_E4M3: return bm >= 256 ? Model{27.8, 8.0, 1.62, 0.2} : Model{0.0, 14.0, 0.82, 0.05};
+        default: return bm >= 256 ? Model{25.2, 8.0, 1.41, 0.2} : Model{0.0, 12.0, 0.73, 0.05};
+        }
+    }
     switch (ab) {
     case SK_F64: return bm >= 128 ? Model{15.6, 4.41, 2.03, 1.65} : Model{6.22, 2.22, 0.73, 0.43};
     case SK_F8_E4M3: return bm >= 256 ? Model{27.8, 0.0, 1.62, 6.39} : Model{0.0, 13.2, 0.82, 0.64};
@@ -202,21 +211,28 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Appendix A.1: g* = argmin over g in [1, min(p, T)] of
 //   a + b [peers > 1] + c ItersPerCta(g) + d (peers - 1),
 // ItersPerCta(g) = ceil(T / g), peers = ceil(I / ItersPerCta(g)); ties take
-// the smallest g.
-int model_grid(int64_t T, int64_t I, int p, const Model &m) {
-    int best_g = 1;
-    double best = 0.0;
+// the smallest g.  `ok(g)` excludes grids the library cannot run (an owner
+// with more than SK_MAX_PEERS peers); g = 1 is always feasible.
+template <class Ok>
+int model_grid(int64_t T, int64_t I, int p, const Model &m, Ok ok) {
     const int64_t gmax = std::max<int64_t>(1, std::min<int64_t>(p, T));
+    std::vector<std::pair<double, int>> cand;
+    cand.reserve((size_t)gmax);
     for (int64_t g = 1; g <= gmax; ++g) {
         const int64_t ipc = cdiv(T, g);
         const int64_t peers = cdiv(I, ipc);
         const double v = m.a + m.b * (peers > 1 ? 1.0 : 0.0) + m.c * (double)ipc + m.d * (double)(peers - 1);
-        if (g == 1 || v < best) {
-            best = v;
-            best_g = (int)g;
-        }
+        cand.push_back({v, (int)g});
     }
-    return best_g;
+    size_t best = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+        if (cand[i].first < cand[best].first) best = i;
+    if (cand[best].second == 1 || ok(cand[best].second)) return cand[best].second;
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const std::pair<double, int> &u, const std::pair<double, int> &v) { return u.first < v.first; });
+    for (const auto &c : cand)
+        if (c.second == 1 || ok(c.second)) return c.second;
+    return 1;
 }
 
 // Host view of one call: problems (kernel form), tile, key and prefix sums.
@@ -239,6 +255,44 @@ struct Call {
     int64_t region_iters(int64_t tb, int64_t te) const {
         if (te <= tb) return 0;
         return (te >= tiles ? iters : tile_iter_begin(te)) - tile_iter_begin(tb);
+    }
+    // [begin, end) in global iterations of the tile holding global iteration it
+    void tile_span(int64_t it, int64_t *b, int64_t *e) const {
+        size_t lo = 0, hi = probs.size();
+        while (hi - lo > 1) {
+            size_t mid = (lo + hi) / 2;
+            if (iter_prefix[mid] <= it) lo = mid; else hi = mid;
+        }
+        // skip problems without tiles (their iteration range is empty)
+        while (lo + 1 < probs.size() && iter_prefix[lo + 1] <= it) ++lo;
+        const int64_t I = probs[lo].iters;
+        *b = iter_prefix[lo] + (it - iter_prefix[lo]) / I * I;
+        *e = *b + I;
+    }
+    // Largest number of peers any tile's owner has when the iterations
+    // [ib, ib + n) are split evenly over g workgroups (section 4 partition).
+    int64_t max_peers(int64_t ib, int64_t n, int64_t g) const {
+        if (n <= 0 || g <= 1) return 0;
+        const int64_t q = n / g, r = n % g, rq = r * (q + 1);
+        auto owner = [&](int64_t i) { return i < rq ? i / (q + 1) : r + (i - rq) / q; };
+        const bool one = probs.size() == 1;
+        const int64_t I1 = probs[0].iters;
+        int64_t best = 0;
+        for (int64_t x = 0; x < g; ++x) {
+            const int64_t b = x * q + std::min(x, r), e = b + q + (x < r ? 1 : 0);
+            if (e <= b) continue;
+            int64_t tb, te;
+            if (one) {
+                tb = (ib + e - 1) / I1 * I1;
+                te = tb + I1;
+            } else {
+                tile_span(ib + e - 1, &tb, &te);
+            }
+            tb -= ib;
+            te -= ib;
+            if (tb >= b && te > e) best = std::max(best, owner(te - 1) - x);
+        }
+        return best;
     }
 };
 
@@ -295,6 +349,17 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
     return SK_OK;
 }
 
+double model_time(int64_t T, int64_t I, int64_t g, const Model &m) {
+    const int64_t ipc = cdiv(T, g);
+    const int64_t peers = cdiv(I, ipc);
+    return m.a + m.b * (peers > 1 ? 1.0 : 0.0) + m.c * (double)ipc + m.d * (double)(peers - 1);
+}
+
+// Owners with at least this many peers make the automatic fixup the spread
+// one (with a single peer the serial fixup moves fewer bytes for the same
+// critical path).
+constexpr int64_t kSpreadMinPeers = 2;
+
 // The schedule: which tiles form the Stream-K region and how many
 // workgroups run.  Section 5.2 hybrids with w = t / p full waves, r = t % p:
 //  r == 0           -> whole waves of data-parallel tiles on g = p;
@@ -302,6 +367,9 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
 //  two-tile SK + DP -> (w >= threshold) SK over the first r + p tiles, each
 //                      workgroup getting 1..2 tiles of iterations, then DP;
 //  DP + one-tile SK -> DP over the first w*p tiles, then SK over the last r.
+// No plan may give a tile's owner more than SK_MAX_PEERS peers: the model's
+// grid search skips such grids, the automatic schedule avoids them, and an
+// explicit grid or hybrid that needs them is rejected.
 sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     std::memset(pl, 0, sizeof(*pl));
     pl->blk_m = c.tile.bm;
@@ -309,14 +377,19 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     pl->blk_k = c.tile.bk;
     pl->tiles = c.tiles;
     pl->iters_total = c.iters;
+    pl->fixup = SK_FIXUP_SERIAL;
     int sched = cfg ? cfg->sched : SK_SCHED_AUTO;
     if (sched < SK_SCHED_AUTO || sched > SK_SCHED_2TILE_SK_DP) return SK_ERR_INVALID_VALUE;
+    const bool auto_sched = sched == SK_SCHED_AUTO;
     const int user_grid = cfg ? cfg->grid : 0;
-    if (user_grid < 0) return SK_ERR_INVALID_VALUE;
+    if (user_grid < 0 || user_grid > SK_MAX_GRID) return SK_ERR_INVALID_VALUE;
+    const int fix_req = cfg ? cfg->fixup : SK_FIXUP_AUTO;
+    if (fix_req < SK_FIXUP_AUTO || fix_req > SK_FIXUP_SPREAD) return SK_ERR_INVALID_VALUE;
     const int threshold = (cfg && cfg->sk_threshold_waves > 0) ? cfg->sk_threshold_waves : 2;
-    Model mc = default_model(c.key.ab_type, c.tile.bm);
+    Model m_serial = default_model(c.key.ab_type, c.tile.bm, false);
+    Model m_spread = default_model(c.key.ab_type, c.tile.bm, true);
     if (cfg && (cfg->model_a != 0.0 || cfg->model_b != 0.0 || cfg->model_c != 0.0 || cfg->model_d != 0.0))
-        mc = Model{cfg->model_a, cfg->model_b, cfg->model_c, cfg->model_d};
+        m_serial = m_spread = Model{cfg->model_a, cfg->model_b, cfg->model_c, cfg->model_d};
     const int64_t t = c.tiles;
     pl->xcd_remap = (cfg && (cfg->flags & SK_FLAG_NO_XCD_REMAP)) ? 0 : 1;
     if (t == 0) {
@@ -338,6 +411,28 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         pl->wg_slots = p;
         if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
     }
+    const int pg = std::min(p, SK_MAX_GRID);   // grids the model may choose
+    // basic Stream-K over every tile: the model's grid for a fixup mode, and
+    // its predicted time
+    auto sk_grid = [&](bool spread, double *val) {
+        const Model &m = spread ? m_spread : m_serial;
+        const int g = model_grid(c.iters, c.imax, pg, m,
+                                 [&](int gg) { return c.max_peers(0, c.iters, gg) <= SK_MAX_PEERS; });
+        if (val) *val = model_time(c.iters, c.imax, g, m);
+        return g;
+    };
+    // the fixup mode and grid of basic Stream-K with the model's grid
+    auto sk_model = [&](int *fix) {
+        if (fix_req == SK_FIXUP_SERIAL) { *fix = SK_FIXUP_SERIAL; return sk_grid(false, nullptr); }
+        if (fix_req == SK_FIXUP_SPREAD) { *fix = SK_FIXUP_SPREAD; return sk_grid(true, nullptr); }
+        double vs = 0.0, vp = 0.0;
+        const int gs = sk_grid(false, &vs), gp = sk_grid(true, &vp);
+        // the spread fixup only for a grid that gives some owner enough peers
+        if (vp < vs && c.max_peers(0, c.iters, gp) >= kSpreadMinPeers) { *fix = SK_FIXUP_SPREAD; return gp; }
+        *fix = SK_FIXUP_SERIAL;
+        return gs;
+    };
+    int fix = SK_FIXUP_SERIAL;
     if (sched == SK_SCHED_AUTO) {
         // Measured on MI355X: Stream-K pays off while the tiles give no CU
         // more than one workgroup (t <= CUs: a lone workgroup leaves its
@@ -356,8 +451,8 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             sched = SK_SCHED_SK;
             // a model grid of exactly one workgroup per tile (one problem)
             // is the data-parallel schedule: run the data-parallel kernel
-            if (user_grid == 0 && c.probs.size() == 1 &&
-                std::min<int64_t>(model_grid(c.iters, c.imax, p, mc), c.iters) == t)
+            int f0 = 0;
+            if (user_grid == 0 && c.probs.size() == 1 && std::min<int64_t>(sk_model(&f0), c.iters) == t)
                 sched = SK_SCHED_DP;
         } else {
             sched = SK_SCHED_DP;
@@ -373,77 +468,128 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     const int64_t w = t / p, r = t % p;
     int64_t skb = 0, ske = 0;
     int64_t g = 0;
+    bool model_g = false;
     if (sched == SK_SCHED_SK || (w == 0 && r != 0)) {
         sched = SK_SCHED_SK;
         skb = 0;
         ske = t;
-        g = user_grid > 0 ? user_grid : model_grid(c.iters, c.imax, p, mc);
+        model_g = user_grid == 0;
+        g = model_g ? sk_model(&fix) : user_grid;
     } else if (r == 0) {
         // perfect quantisation: data-parallel waves only
         sched = SK_SCHED_DP_1TILE_SK;
         skb = ske = 0;
-        g = user_grid > 0 ? user_grid : p;
+        g = user_grid > 0 ? user_grid : pg;
     } else if (sched == SK_SCHED_2TILE_SK_DP && w >= threshold) {
         skb = 0;
         ske = r + p;
-        g = user_grid > 0 ? user_grid : p;
+        g = user_grid > 0 ? user_grid : pg;
     } else {
         sched = SK_SCHED_DP_1TILE_SK;
         skb = w * p;
         ske = t;
-        g = user_grid > 0 ? user_grid : p;
+        g = user_grid > 0 ? user_grid : pg;
     }
-    const int64_t sk_iters = c.region_iters(skb, ske);
+    int64_t sk_iters = c.region_iters(skb, ske);
     // basic Stream-K never launches more workgroups than iterations; a
     // hybrid's grid also carries its data-parallel waves and keeps p (some
     // workgroups then have an empty Stream-K range)
     if (sched == SK_SCHED_SK && sk_iters > 0) g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
+    int64_t sk_ib = skb < t ? c.tile_iter_begin(skb) : c.iters;
+    int64_t mp = c.max_peers(sk_ib, sk_iters, g);
+    if (mp > SK_MAX_PEERS) {
+        // only a hybrid the automatic schedule chose (or an explicit grid)
+        // gets here: the automatic schedule falls back to basic Stream-K
+        if (!auto_sched || user_grid > 0) return SK_ERR_UNSUPPORTED;
+        sched = SK_SCHED_SK;
+        skb = 0;
+        ske = t;
+        model_g = true;
+        g = sk_model(&fix);
+        sk_iters = c.iters;
+        g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
+        sk_ib = 0;
+        mp = c.max_peers(0, sk_iters, g);
+    }
+    if (!model_g) {
+        fix = fix_req == SK_FIXUP_AUTO ? (mp >= kSpreadMinPeers ? SK_FIXUP_SPREAD : SK_FIXUP_SERIAL) : fix_req;
+    }
     pl->sched = sched;
     pl->grid = (int32_t)g;
     pl->dp_first = sched == SK_SCHED_DP_1TILE_SK ? 1 : 0;
     pl->sk_tile_begin = skb;
     pl->sk_tile_end = ske;
-    pl->sk_iter_begin = skb < t ? c.tile_iter_begin(skb) : c.iters;
+    pl->sk_iter_begin = sk_ib;
     pl->sk_iters = sk_iters;
     pl->dp_tiles = t - (ske - skb);
+    pl->fixup = fix;
+    pl->max_peers = (int32_t)mp;
     return SK_OK;
 }
 
 struct Layout {
-    size_t flags = 0, partials = 0, raw = 0, probs = 0, tpre = 0, ipre = 0, total = 0;
+    size_t partials = 0, raw = 0, probs = 0, tpre = 0, ipre = 0, total = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// The descriptor-table region is always reserved (a few hundred bytes per
+// Workspace: the header words, the fixed flag region (reserved in every
+// workspace, so no table or partial tile is ever stored where a later call
+// looks for flags), the partial-tile slots of a Stream-K plan (g of them for
+// the serial fixup, 2g for the spread one), then the grouped descriptor
+// tables.  The table region is always reserved (a few hundred bytes per
 // problem), so one size serves sk_gemm and sk_gemm_grouped alike, including
 // a grouped call with a single problem.
-Layout layout_for(const sk_plan_t &pl, int ab, int32_t count, bool grouped) {
-    grouped = true;
+Layout layout_for(const sk_plan_t &pl, int ab, int32_t count) {
     Layout L;
-    size_t off = WS_HEADER;
+    size_t off = WS_HEADER + FLAG_REGION;
     if (pl.sched != SK_SCHED_DP && pl.grid > 0) {
-        L.flags = off;
-        off = align256(off + (size_t)pl.grid * FLAG_STRIDE * sizeof(int32_t));
         L.partials = off;
         const size_t acc = ab == SK_F64 ? 8 : 4;
-        off = align256(off + (size_t)pl.grid * pl.blk_m * pl.blk_n * acc);
+        const size_t slots = (size_t)pl.grid * (pl.fixup == SK_FIXUP_SPREAD ? 2 : 1);
+        off = align256(off + slots * pl.blk_m * pl.blk_n * acc);
     }
-    if (grouped) {
-        L.raw = off;
-        off = align256(off + (size_t)count * sizeof(sk_gemm_desc_t));
-        L.probs = off;
-        off = align256(off + (size_t)count * sizeof(Problem));
-        L.tpre = off;
-        off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
-        L.ipre = off;
-        off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
-    }
+    L.raw = off;
+    off = align256(off + (size_t)count * sizeof(sk_gemm_desc_t));
+    L.probs = off;
+    off = align256(off + (size_t)count * sizeof(Problem));
+    L.tpre = off;
+    off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
+    L.ipre = off;
+    off = align256(off + (size_t)(count + 1) * sizeof(int32_t));
     L.total = off;
     return L;
 }
 
-constexpr int kSpinLimit = 1 << 22;
+// Bound of one fixup wait when the caller gives none: 2 s of real time.
+constexpr int64_t kWaitLimitUs = 2000000;
+
+// Ticks per microsecond of the counter the kernels read for their bounded
+// waits (s_memrealtime), per device.
+std::vector<std::pair<int, int64_t>> g_clock_cache;
+
+int64_t wait_ticks(const sk_config_t *cfg) {
+    const int64_t us = (cfg && cfg->wait_limit_us != 0) ? cfg->wait_limit_us : kWaitLimitUs;
+    if (us < 0) return 0;
+    int dev = 0;
+    int64_t khz = 100000;    // 100 MHz unless the device says otherwise
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        bool found = false;
+        for (auto &e : g_clock_cache)
+            if (e.first == dev) {
+                khz = e.second;
+                found = true;
+            }
+        if (!found) {
+            int rate = 0;
+            if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
+                khz = rate;
+            g_clock_cache.push_back({dev, khz});
+        }
+    }
+    return std::max<int64_t>(1, us * khz / 1000);
+}
 
 // Tile rasterisation: bands of this many tile rows, walked column by column,
 // so consecutive tiles (and the workgroups of one XCD) share A and B panels.
@@ -464,10 +610,11 @@ Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws
     P.dp_first = pl.dp_first;
     P.xcd_remap = pl.xcd_remap;
     P.band = (cfg && (cfg->flags & SK_FLAG_ROW_MAJOR_TILES)) ? 1 : kTileBand;
-    P.spin_limit = kSpinLimit;
+    P.fixup = pl.fixup == SK_FIXUP_SPREAD ? FIXUP_SPREAD : FIXUP_SERIAL;
+    P.wait_ticks = wait_ticks(cfg);
     char *w = (char *)ws;
-    P.err = (int32_t *)w;
-    if (L.flags) P.flags = (int32_t *)(w + L.flags);
+    P.hdr = (int32_t *)w;
+    P.flags = (int32_t *)(w + WS_HEADER);
     if (L.partials) P.partials = w + L.partials;
     if (cfg && cfg->trace) {
         P.trace = cfg->trace;
@@ -500,7 +647,7 @@ sk_status_t sk_plan(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *c
     if (s != SK_OK) return s;
     s = plan_call(c, cfg, out);
     if (s != SK_OK) return s;
-    out->workspace_bytes = layout_for(*out, d[0].ab_type, count, count > 1).total;
+    out->workspace_bytes = layout_for(*out, d[0].ab_type, count).total;
     return SK_OK;
 }
 
@@ -529,7 +676,7 @@ sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *works
     sk_plan_t pl;
     s = plan_call(c, cfg, &pl);
     if (s != SK_OK) return s;
-    Layout L = layout_for(pl, d->ab_type, 1, false);
+    Layout L = layout_for(pl, d->ab_type, 1);
     if (!workspace || ws_bytes < L.total) return SK_ERR_WORKSPACE_TOO_SMALL;
     KernelKey key = c.key;
     key.dp_only = pl.sched == SK_SCHED_DP;
@@ -547,7 +694,7 @@ sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count, const sk_con
     sk_plan_t pl;
     s = plan_call(c, cfg, &pl);
     if (s != SK_OK) return s;
-    Layout L = layout_for(pl, d[0].ab_type, count, true);
+    Layout L = layout_for(pl, d[0].ab_type, count);
     if (!workspace || ws_bytes < L.total) return SK_ERR_WORKSPACE_TOO_SMALL;
     if (c.tiles == 0) return SK_OK;
     KernelKey key = c.key;
@@ -572,13 +719,18 @@ sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count, const sk_con
 }
 
 sk_status_t sk_workspace_check(void *workspace, size_t ws_bytes, void *stream) {
-    if (!workspace || ws_bytes < (size_t)WS_HEADER) return SK_ERR_INVALID_VALUE;
+    if (!workspace || ws_bytes < (size_t)(WS_HEADER + FLAG_REGION)) return SK_ERR_INVALID_VALUE;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SK_ERR_HIP;
     int32_t err = 0;
     if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return SK_ERR_HIP;
     if (err == 0) return SK_OK;
-    const int32_t zero = 0;
-    if (hipMemcpy(workspace, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return SK_ERR_HIP;
+    // A wait gave up.  Every workgroup still finished and the generation
+    // moved on, so no flag of that call can be mistaken for a later call's;
+    // the header and the flag region are reset anyway, to the state of a
+    // freshly zeroed workspace.
+    if (hipMemsetAsync(workspace, 0, (size_t)(WS_HEADER + FLAG_REGION), (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return SK_ERR_HIP;
     return SK_ERR_TIMEOUT;
 }
 

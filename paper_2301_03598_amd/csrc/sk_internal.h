@@ -89,19 +89,35 @@ struct Params {
     int32_t dp_first;
     int32_t xcd_remap;
     int32_t band;            // tile rasterisation band (1: row-major tiles)
-    int32_t spin_limit;      // bounded fixup wait (polls)
-    void *partials;          // g slots of BM*BN accumulators
-    int32_t *flags;          // g flags, FLAG_STRIDE ints apart
-    int32_t *err;            // sticky error word
+    int32_t fixup;           // FIXUP_SERIAL or FIXUP_SPREAD
+    int64_t wait_ticks;      // bound of one fixup wait, in real-time-counter ticks (<= 0: give up at once)
+    void *partials;          // partial-tile slots of BM*BN accumulators (see slot_first / slot_last)
+    int32_t *flags;          // the fixed flag region, FLAG_STRIDE ints apart
+    int32_t *hdr;            // workspace header: HDR_ERR, HDR_GEN, HDR_DONE
     int32_t *trace;          // optional segment trace
     int64_t trace_cap;
 };
 
 constexpr int FLAG_STRIDE = 16;          // ints between flags (64 bytes)
-constexpr int WS_HEADER = 256;           // error word and padding
+constexpr int WS_HEADER = 256;           // header words and padding
 constexpr int THREADS = 256;             // 4 wave64 per workgroup
+constexpr int MAX_GRID = 1024;           // largest persistent grid
+// The flag region [WS_HEADER, WS_HEADER + FLAG_REGION) is reserved in every
+// workspace whatever the schedule, so nothing but flags is ever stored there:
+// flag x (x < MAX_GRID) belongs to the partial tile workgroup x stores for
+// its first segment, flag MAX_GRID + x to the one it stores for its last
+// segment (distributed fixup only).
+constexpr int FLAG_REGION = 2 * MAX_GRID * FLAG_STRIDE * 4;
+// Header words.  A flag is raised by storing the call's epoch, derived from
+// HDR_GEN, so flags never need clearing; the last workgroup of a Stream-K
+// launch to finish (counted in HDR_DONE) advances HDR_GEN for the next call.
+constexpr int HDR_ERR = 0, HDR_GEN = 1, HDR_DONE = 2;
+// Owners wait on at most this many peers (one 64-lane polling round).
+constexpr int MAX_PEERS = 64;
 
-enum Role { ROLE_DP = 0, ROLE_FULL = 1, ROLE_OWNER = 2, ROLE_PRODUCER = 3 };
+enum Fixup { FIXUP_SERIAL = 0, FIXUP_SPREAD = 1 };
+
+enum Role { ROLE_DP = 0, ROLE_FULL = 1, ROLE_OWNER = 2, ROLE_PRODUCER = 3, ROLE_REDUCE = 4 };
 
 // Kernel instance selection key.
 struct KernelKey {

@@ -989,41 +989,48 @@ __device__ __forceinline__ void store_partial(char *slot, const typename C::Frag
 // ---------------------------------------------------------------------------
 // flags.  Partial tiles and flags are all device-coherent accesses (SC1):
 // the producer waits until its partial stores have completed, then one
-// thread raises the flag; the owner polls its peers' flags (one lane per
-// peer) and issues its partial loads only after it has seen all of them.  Program order plus completion waits
-// order the accesses; no cache-wide fence is needed.
+// thread raises the flag by storing the call's epoch; a waiter polls the
+// flags it needs (one lane per flag) and issues its partial loads only after
+// it has seen all of them.  Program order plus completion waits order the
+// accesses; no cache-wide fence is needed.  A flag is never cleared: a value
+// other than this call's epoch (an earlier call's, or zero) means "not yet".
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void signal_flag(int32_t *flag, int tid) {
+__device__ __forceinline__ void signal_flag(int32_t *flag, int32_t epoch, int tid) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's partial stores are done
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until the flags of peers first..last are all raised, then clear them.
-// Wave 0 polls up to 64 peers per round, one per lane, so a round costs one
-// load latency however many peers there are; the other waves wait at the
-// barrier.  Bounded: after `limit` polls the error word is set and the wait
-// ends (the partial tiles of a peer that never arrived are then garbage and
-// the call reports SK_ERR_TIMEOUT).
-__device__ __forceinline__ void wait_flags(int32_t *flags, int first, int last, int32_t *err, int limit, int tid) {
+// Wait until the flags of contributors first..last other than `self` (at
+// most MAX_PEERS of them, one per lane of wave 0) all hold `epoch`.
+// Contributor c's flag is flags[c], except that contributor `first` uses
+// flags[first_flag].  The other waves wait at the barrier.  Bounded in real
+// time: once `ticks` of the constant-rate counter have passed (at once if
+// ticks <= 0) the error word is set and the wait ends; the partial tiles of a
+// contributor that has not arrived are then stale and the call reports
+// SK_ERR_TIMEOUT.
+__device__ __forceinline__ void wait_flags(const int32_t *flags, int first, int last, int self, int first_flag,
+                                           int32_t epoch, int32_t *err, int64_t ticks, int tid) {
     if (tid < 64) {
-        for (int base = first; base <= last; base += 64) {
-            const int peer = base + tid;
-            const bool mine = peer <= last;
-            int32_t *f = flags + (int64_t)(mine ? peer : first) * FLAG_STRIDE;
-            bool seen = !mine;
-            int n = 0;
+        const int c = first + tid + (first + tid >= self && self >= first ? 1 : 0);
+        const bool mine = c <= last;
+        const int fi = c == first ? first_flag : c;
+        const int32_t *f = flags + (int64_t)(mine ? fi : first_flag) * FLAG_STRIDE;
+        bool seen = !mine;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        if (ticks > 0) {
             while (true) {
-                if (!seen) seen = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (!seen) seen = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
                 if (__all(seen)) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (++n >= limit) {         // bounded: give up, report, never hang
-                    if (tid == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > ticks) {
+                    seen = false;
                     break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
-            if (mine) __hip_atomic_store(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // consumed
         }
+        // bounded: give up, report, never hang
+        if (!__all(seen) && tid == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // the workgroup barrier (with its compiler-level ordering) keeps every
     // wave's partial loads behind the observed flags
@@ -1031,16 +1038,154 @@ __device__ __forceinline__ void wait_flags(int32_t *flags, int first, int last, 
 }
 
 __device__ __forceinline__ void trace_rec(const Params &p, int wg, int seq, int tile, int k0, int k1,
-                                          int role, int last, int tid) {
+                                          int role, int last, int extra, int tid) {
     if (p.trace != nullptr && tid == 0) {
         int idx = __hip_atomic_fetch_add(p.trace, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (idx < p.trace_cap) {
             int32_t *rec = p.trace + 8 + (int64_t)idx * 8;
             rec[0] = wg; rec[1] = seq; rec[2] = tile; rec[3] = k0;
-            rec[4] = k1; rec[5] = role; rec[6] = last; rec[7] = 0;
+            rec[4] = k1; rec[5] = role; rec[6] = last; rec[7] = extra;
         }
     }
 }
+
+// ---------------------------------------------------------------------------
+// Distributed fixup: every contributor of a split tile stores its partial
+// tile, and contributor f + i of the s = l - f + 1 contributors f..l reduces
+// chunks [i N / s, (i + 1) N / s) of the tile's N 16-byte partial chunks over
+// all s partials, in ascending workgroup order -- the same additions, in the
+// same order, as the owner's serial fixup, so both give identical bits --
+// then applies alpha / beta and writes those elements of C.  The slices of a
+// pass are staged into the (idle) MAC-loop LDS buffers with LDS-DMA loads,
+// all contributors' chunks at once, so the reads of one slice take one
+// memory round trip instead of one per contributor.
+// ---------------------------------------------------------------------------
+template <class C>
+struct Spread {
+    static constexpr int N = C::SLOT_BYTES / 16;                 // chunks per tile
+    static constexpr int LDS_CHUNKS = C::NSTAGE * C::STAGE / 16;  // staging capacity
+    static constexpr int BLK_PER_BUF = C::STAGE / 1024;           // 1 KiB DMA blocks per buffer
+    static_assert(C::STAGE % 1024 == 0, "whole DMA blocks per buffer");
+
+    __device__ static __forceinline__ char *blk(LdsBufs b, int i) {
+        const int u = i / BLK_PER_BUF, o = (i % BLK_PER_BUF) * 1024;
+        return (u == 0 ? b.b0 : u == 1 ? b.b1 : b.b2) + o;
+    }
+
+    // Elements of chunk c (16 bytes of the thread-fragment order) of tile
+    // (tm, tn): alpha * v (+ beta * C), rounded once, masked at the edges.
+    template <int CT>
+    __device__ static __forceinline__ void put_chunk(const Problem &P, int tm, int tn, int c, const u32x4 &raw) {
+        using Acc = typename C::Acc;
+        using PL = PartialLayout<C>;
+        constexpr int EB = CBytes<CT>::v;
+        const int t = c % THREADS, vi = c / THREADS;
+        const int sc = vi % PL::CPF, fij = vi / PL::CPF, fi = fij / C::FN, fj = fij % C::FN;
+        const int lane = t & 63, wave = t >> 6, wm = wave >> 1, wn = wave & 1;
+        const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
+        const bool rd = P.beta != 0.0;
+        if constexpr (C::MT == 16) {
+            // FP64: the chunk holds rows 4(2 sc) + lane/16 and 4(2 sc + 1) + lane/16 of one column
+            const f64x2 v = __builtin_bit_cast(f64x2, raw);
+            const int col = tn * C::BN + wn * C::WTN + fj * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int row = tm * C::BM + wm * C::WTM + fi * 16 + 4 * (2 * sc + e) + (lane >> 4);
+                if (row < P.m && col < P.n) {
+                    char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+                    Acc w = alpha * v[e];
+                    if (rd) w = w + beta * load_c<CT, Acc>(q);
+                    put_c<CT, Acc>(q, w);
+                }
+            }
+        } else {
+            // 32x32 blocks: four consecutive columns of one row
+            const f32x4 v = __builtin_bit_cast(f32x4, raw);
+            const int row = tm * C::BM + wm * C::WTM + fi * C::MT + (lane % C::MT);
+            const int col = tn * C::BN + wn * C::WTN + fj * C::MT + 8 * sc + 4 * (lane / C::MT);
+            char *rp = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+            Acc a[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[e] = alpha * v[e];
+            const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
+            if (P.c_vec && interior) {
+                put4<CT, Acc>(rp, a, beta, rd);
+            } else if (row < P.m) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (col + e < P.n) {
+                        char *q = rp + e * EB;
+                        Acc w = a[e];
+                        if (rd) w = w + beta * load_c<CT, Acc>(q);
+                        put_c<CT, Acc>(q, w);
+                    }
+                }
+            }
+        }
+    }
+
+    template <int CT>
+    __device__ static __forceinline__ void reduce_t(const Params &p, const Problem &P, int tm, int tn, int f,
+                                                    int l, int x, LdsBufs bufs, int tid) {
+        const int s = l - f + 1, i = x - f;
+        const int c0 = (int)((int64_t)N * i / s), c1 = (int)((int64_t)N * (i + 1) / s);
+        // chunks per pass: all s contributors' copies of them fit the LDS
+        const int pc = LDS_CHUNKS / s;
+        const uint32_t region = (uint32_t)(2 * p.g) * (uint32_t)C::SLOT_BYTES;
+        const __amdgpu_buffer_rsrc_t rs = slot_rsrc((const char *)p.partials, (int)region);
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6), L = tid & 63;
+        for (int cp = c0; cp < c1; cp += pc) {
+            const int n = c1 - cp < pc ? c1 - cp : pc;         // chunks this pass
+            const int nblk = (s * pc + 63) / 64;              // 1 KiB staging blocks
+            __syncthreads();                                   // LDS free (MAC loop / previous pass)
+            for (int b = w; b < nblk; b += 4) {
+                const int k = b * 64 + L;                      // staging index: contributor k / pc, chunk k % pc
+                const int cc = k / pc, j = k % pc;
+                const int slot = cc == 0 ? p.g + f : f + cc;   // the owner's is its last-segment slot
+                const bool ok = cc < s && j < n;
+                const uint32_t off = ok ? (uint32_t)slot * (uint32_t)C::SLOT_BYTES + (uint32_t)(cp + j) * 16u
+                                        : 0x80000000u;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)blk(bufs, b),
+                                                         16, off, 0, 0, CPOL_DEVICE);
+            }
+            wait_dma();
+            __syncthreads();
+            for (int j = tid; j < n; j += THREADS) {
+                u32x4 raw;
+                if constexpr (sizeof(typename C::Acc) == 4) {
+                    f32x4 v = *(const f32x4 *)(blk(bufs, j / 64) + (j % 64) * 16);
+                    for (int cc = 1; cc < s; ++cc) {
+                        const int k = cc * pc + j;
+                        v = v + *(const f32x4 *)(blk(bufs, k / 64) + (k % 64) * 16);
+                    }
+                    raw = __builtin_bit_cast(u32x4, v);
+                } else {
+                    f64x2 v = *(const f64x2 *)(blk(bufs, j / 64) + (j % 64) * 16);
+                    for (int cc = 1; cc < s; ++cc) {
+                        const int k = cc * pc + j;
+                        v = v + *(const f64x2 *)(blk(bufs, k / 64) + (k % 64) * 16);
+                    }
+                    raw = __builtin_bit_cast(u32x4, v);
+                }
+                put_chunk<CT>(P, tm, tn, cp + j, raw);
+            }
+        }
+        __syncthreads();                                       // LDS free for the next user
+    }
+
+    __device__ static __forceinline__ void reduce(const Params &p, const Problem &P, int tm, int tn, int f, int l,
+                                                  int x, LdsBufs bufs, int tid) {
+        if constexpr (C::DT == Dt::F64) {
+            reduce_t<SK_F64>(p, P, tm, tn, f, l, x, bufs, tid);
+        } else {
+            switch (P.c_type) {
+            case SK_F32: reduce_t<SK_F32>(p, P, tm, tn, f, l, x, bufs, tid); break;
+            case SK_F16: reduce_t<SK_F16>(p, P, tm, tn, f, l, x, bufs, tid); break;
+            default: reduce_t<SK_BF16>(p, P, tm, tn, f, l, x, bufs, tid); break;
+            }
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // tile lookup
@@ -1125,9 +1270,20 @@ __device__ __forceinline__ int tile_of_iter(const Params &p, int it) {
 // (j = x, x+g, ...) and the segments of its Stream-K range, in the phase
 // order the plan asks for.  Keeping a single MAC-loop / fixup / epilogue site
 // keeps the code (and its register allocation) in one piece.
+//
+// Fixup of a tile split over workgroups f..l (f owns the tile's k = 0):
+//  serial (Algorithm 5): f..l-1's successors f+1..l store their partial tiles
+//    and raise their flags; f waits for them and adds them to its own
+//    accumulators in ascending order inside its epilogue;
+//  spread: every contributor stores its partial tile and raises its flag as
+//    its segment ends; after its last unit, each contributor waits for the
+//    tile's other contributors and reduces its slice (Spread).  Only the
+//    first and the last segment of a range can belong to a split tile, so a
+//    workgroup has at most two slices to reduce; its partial tiles live in
+//    slots x (first segment) and g + x (last segment).
 template <class C, bool DP_ONLY>
 __device__ __forceinline__ void sk_body(const Params &p) {
-    // the two k-tile buffers of the MAC loop
+    // the k-tile buffers of the MAC loop
     __shared__ __attribute__((aligned(16))) char lds0[C::STAGE];
     __shared__ __attribute__((aligned(16))) char lds1[C::STAGE];
     __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE >= 3 ? C::STAGE : 16];
@@ -1142,6 +1298,14 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         const int q8 = p.g >> 3, r8 = p.g & 7, j = b & 7;
         x = j * q8 + (j < r8 ? j : r8) + (b >> 3);
     }
+    // this call's flag value: the generation word is only advanced after
+    // every workgroup of the launch has finished, so all read the same value
+    int32_t epoch = 0;
+    if constexpr (!DP_ONLY) {
+        const uint32_t gen = (uint32_t)__hip_atomic_load(p.hdr + HDR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        epoch = uniform_int((int)((gen & 0x3fffffffu) + 1u));
+    }
+    const bool spread = !DP_ONLY && p.fixup == FIXUP_SPREAD;
     // Stream-K range of this workgroup: [beg, end) within the SK region
     int q = 0, r = 0, beg = 0, end = 0, rq = 0;
     if (!DP_ONLY && p.sk_iters > 0) {
@@ -1151,6 +1315,10 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         end = beg + q + (x < r ? 1 : 0);
         rq = r * (q + 1);
     }
+    // the workgroup holding region-relative iteration i
+    auto owner_of = [&](int i) { return i < rq ? i / (q + 1) : r + (i - rq) / q; };
+    // slices still to reduce (spread fixup): tile, first and last contributor
+    int red_tile[2] = {-1, -1}, red_f[2] = {0, 0}, red_l[2] = {0, 0};
     int it = beg;          // next SK iteration
     int j = x;             // next DP tile index
     int phase = 0;         // 0, 1: the two phases; 2: done
@@ -1171,12 +1339,12 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         }
         const TileRef tr = tile_of_tile<C::GROUPED>(p, tile);
         const Problem P = uniform_problem(*tr.P);
-        int t1 = 0;
+        int t0 = 0, t1 = 0;
         if (dp_now) {
             k0 = 0;
             k1 = P.iters;
         } else {
-            const int t0 = uniform_int(tr.it_begin) - p.sk_iter_begin;   // region-relative tile start
+            t0 = uniform_int(tr.it_begin) - p.sk_iter_begin;   // region-relative tile start
             t1 = t0 + P.iters;
             k0 = it - t0;
             k1 = (end < t1 ? end : t1) - t0;
@@ -1193,23 +1361,63 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         asm volatile("" : "+v"(tid));
         typename C::Frag acc[C::FM][C::FN];
         mac_loop<C>(P, tm, tn, k0, k1, acc, bufs, tid);
+        const int last = ended ? -1 : owner_of(t1 - 1);
         if (!started) {
+            // the first segment of this range: partial slot and flag x
             store_partial<C>((char *)p.partials + (int64_t)x * C::SLOT_BYTES, acc, tid);
-            signal_flag(p.flags + x * FLAG_STRIDE, tid);
-            trace_rec(p, x, seq++, tile, k0, k1, ROLE_PRODUCER, -1, tid);
+            signal_flag(p.flags + x * FLAG_STRIDE, epoch, tid);
+            trace_rec(p, x, seq++, tile, k0, k1, ROLE_PRODUCER, -1, 0, tid);
+            if (spread) {
+                red_tile[0] = tile;
+                red_f[0] = owner_of(t0);
+                red_l[0] = ended ? x : last;
+            }
             continue;
         }
-        int last = -1;
-        if (!ended) {
-            const int li = t1 - 1;
-            last = li < rq ? li / (q + 1) : r + (li - rq) / q;
-            wait_flags(p.flags, x + 1, last, p.err, p.spin_limit, tid);
+        if (!ended && spread) {
+            // the last segment of this range owns the tile: partial slot and
+            // flag g + x (resp. MAX_GRID + x)
+            store_partial<C>((char *)p.partials + (int64_t)(p.g + x) * C::SLOT_BYTES, acc, tid);
+            signal_flag(p.flags + (MAX_GRID + x) * FLAG_STRIDE, epoch, tid);
+            trace_rec(p, x, seq++, tile, k0, k1, ROLE_OWNER, last, 0, tid);
+            red_tile[1] = tile;
+            red_f[1] = x;
+            red_l[1] = last;
+            continue;
         }
+        if (!ended) wait_flags(p.flags, x + 1, last, -1, x + 1, epoch, p.hdr + HDR_ERR, p.wait_ticks, tid);
         // peers' partial tiles are added in ascending slot order inside the
         // epilogue, fragment by fragment
         store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last, lds0, lds1);
-        trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER),
-                  last, tid);
+        trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER), last, 0,
+                  tid);
+    }
+    if constexpr (!DP_ONLY) {
+        if (spread) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (red_tile[u] < 0) continue;
+                const int f = red_f[u], l = red_l[u];
+                wait_flags(p.flags, f, l, x, MAX_GRID + f, epoch, p.hdr + HDR_ERR, p.wait_ticks, tid0);
+                const TileRef tr = tile_of_tile<C::GROUPED>(p, red_tile[u]);
+                const Problem P = uniform_problem(*tr.P);
+                int tm, tn;
+                tile_coords(P, uniform_int(tr.tile_local), p.band, tm, tn);
+                const int s = l - f + 1, i = x - f;
+                trace_rec(p, x, seq++, red_tile[u], (int)((int64_t)Spread<C>::N * i / s),
+                          (int)((int64_t)Spread<C>::N * (i + 1) / s), ROLE_REDUCE, l, f, tid0);
+                Spread<C>::reduce(p, P, tm, tn, f, l, x, bufs, tid0);
+            }
+        }
+        // the last workgroup to finish advances the generation (next epoch)
+        __syncthreads();
+        if (tid0 == 0) {
+            const int done = __hip_atomic_fetch_add(p.hdr + HDR_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (done == p.g - 1) {
+                __hip_atomic_store(p.hdr + HDR_DONE, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(p.hdr + HDR_GEN, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
 }
 

@@ -88,9 +88,9 @@ def gemm_grouped(descs: Sequence[S.sk_gemm_desc_t], *, cfg: Optional[S.sk_config
 
 
 def read_trace(buf: torch.Tensor):
-    """Decode a segment trace buffer: list of (wg, seq, tile, k0, k1, role, last)."""
+    """Decode a segment trace buffer: list of (wg, seq, tile, k0, k1, role, last, x)."""
     host = buf.cpu()
     count = int(host[0])
     cap = (host.numel() - 8) // 8
     recs = host[8:8 + 8 * min(count, cap)].view(-1, 8).tolist()
-    return count, [tuple(r[:7]) for r in recs]
+    return count, [tuple(r) for r in recs]

@@ -22,6 +22,10 @@ SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_SCHED_AUTO, SK_SCHED_DP, SK_SCHED_SK, SK_SCHED_DP_1TILE_SK, SK_SCHED_2TILE_SK_DP = range(5)
 SK_FLAG_NO_XCD_REMAP = 0x1
 SK_FLAG_ROW_MAJOR_TILES = 0x2
+SK_MAX_GRID, SK_MAX_PEERS = 1024, 64
+SK_FIXUP_AUTO, SK_FIXUP_SERIAL, SK_FIXUP_SPREAD = 0, 1, 2
+FIXUP = {"auto": SK_FIXUP_AUTO, "serial": SK_FIXUP_SERIAL, "spread": SK_FIXUP_SPREAD}
+FIXUP_NAME = {v: k for k, v in FIXUP.items()}
 
 DTYPE = {"f64": SK_F64, "f32": SK_F32, "f16": SK_F16, "bf16": SK_BF16, "f8e4m3": SK_F8_E4M3}
 ORDER = {"row": SK_ROW_MAJOR, "col": SK_COL_MAJOR}
@@ -50,7 +54,8 @@ class sk_config_t(ctypes.Structure):
                 ("flags", c_int32),
                 ("model_a", c_double), ("model_b", c_double), ("model_c", c_double),
                 ("model_d", c_double),
-                ("trace", c_void_p), ("trace_capacity", c_int64)]
+                ("trace", c_void_p), ("trace_capacity", c_int64),
+                ("wait_limit_us", c_int32), ("fixup", c_int32), ("model_bw", c_double)]
 
 
 class sk_plan_t(ctypes.Structure):
@@ -60,7 +65,8 @@ class sk_plan_t(ctypes.Structure):
                 ("tiles", c_int64), ("iters_total", c_int64),
                 ("sk_tile_begin", c_int64), ("sk_tile_end", c_int64),
                 ("sk_iter_begin", c_int64), ("sk_iters", c_int64),
-                ("dp_tiles", c_int64), ("workspace_bytes", c_uint64)]
+                ("dp_tiles", c_int64), ("workspace_bytes", c_uint64),
+                ("fixup", c_int32), ("max_peers", c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -185,8 +191,11 @@ def make_desc(m, n, k, A, B, C, *, ab_type, c_type, a_order="row", b_order="row"
 
 
 def make_config(sched="auto", blk=None, grid=0, wg_slots=0, threshold=0, flags=0,
-                model=None, trace_ptr=0, trace_capacity=0) -> sk_config_t:
+                model=None, trace_ptr=0, trace_capacity=0, fixup="auto",
+                wait_limit_us=0) -> sk_config_t:
     c = sk_config_t()
+    c.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
+    c.wait_limit_us = int(wait_limit_us)
     c.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     if blk is not None:
         c.blk_m, c.blk_n = int(blk[0]), int(blk[1])

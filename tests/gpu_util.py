@@ -111,15 +111,53 @@ def oracle_segments(plan, shapes, c_order="row"):
     return segs
 
 
-def compare_trace(trace, plan, shapes, c_order="row"):
+ROLE_REDUCE = 4
+
+
+def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4):
+    """The executed segments must be the schedule oracle's, record by record.
+    Slice reductions of the spread fixup (role 4) are checked separately:
+    every split tile's partial chunks are reduced exactly once, by each of its
+    contributors in turn, in ascending slices."""
     count, recs = trace
     segs = oracle_segments(plan, shapes, c_order)
+    seg_recs = [r for r in recs if r[5] != ROLE_REDUCE]
+    red_recs = [r for r in recs if r[5] == ROLE_REDUCE]
     expect = sum(len(l) for l in segs)
-    assert count == expect, f"trace has {count} records, oracle {expect}"
+    assert len(seg_recs) == expect, f"trace has {len(seg_recs)} segment records, oracle {expect}"
     got = {}
-    for (wg, seq, tile, k0, k1, role, last) in recs:
+    for (wg, seq, tile, k0, k1, role, last, _x) in seg_recs:
         got.setdefault(wg, []).append((seq, tile, k0, k1, role, last))
     for x, lst in enumerate(segs):
         mine = [r[1:] for r in sorted(got.get(x, []))]
         want = [(s.tile, s.k_begin, s.k_end, s.role, s.peers[-1] if s.peers else -1) for s in lst]
         assert mine == want, f"workgroup {x}: {mine[:4]} != {want[:4]}"
+    split = {}
+    for lst in segs:
+        for sg in lst:
+            if sg.role == O.ROLE_OWNER:
+                split[sg.tile] = (sg.wg, sg.peers[-1])
+    if plan.fixup != S.SK_FIXUP_SPREAD:
+        assert not red_recs, "slice reductions in a serial-fixup launch"
+        return
+    nchunks = plan.blk_m * plan.blk_n * acc_bytes // 16
+    by_tile = {}
+    for (wg, seq, tile, c0, c1, role, last, first) in red_recs:
+        by_tile.setdefault(tile, []).append((wg, c0, c1, first, last))
+    assert set(by_tile) == set(split), "reduced tiles differ from the split tiles"
+    for tile, lst in by_tile.items():
+        f, l = split[tile]
+        lst.sort()
+        assert [r[0] for r in lst] == list(range(f, l + 1)), f"tile {tile}: reducers {[r[0] for r in lst]}"
+        assert all(r[3] == f and r[4] == l for r in lst)
+        pos = 0
+        for (wg, c0, c1, _f, _l) in lst:
+            assert c0 == pos and c1 > c0, f"tile {tile}: slice [{c0},{c1}) after {pos}"
+            pos = c1
+        assert pos == nchunks, f"tile {tile}: slices end at {pos}, not {nchunks}"
+
+
+def ws_header(ws):
+    """(error word, generation, done counter) of a workspace."""
+    h = ws.buf[:12].view(torch.int32).cpu().tolist()
+    return tuple(h)

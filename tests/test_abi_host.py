@@ -34,10 +34,29 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(S.sk_gemm_desc_t) == 120
-    assert ctypes.sizeof(S.sk_config_t) == 80
-    assert ctypes.sizeof(S.sk_plan_t) == 96
+def test_struct_layouts_match_header():
+    # compile the C header with the host compiler and compare every struct's
+    # size and field offsets with the ctypes binding
+    import subprocess
+    import tempfile
+    structs = {"sk_gemm_desc_t": S.sk_gemm_desc_t, "sk_config_t": S.sk_config_t, "sk_plan_t": S.sk_plan_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "streamk.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append('printf("SK_MAX_GRID %d\\nSK_MAX_PEERS %d\\n", SK_MAX_GRID, SK_MAX_PEERS); return 0; }')
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    got = dict(zip(out[0::2], (int(v) for v in out[1::2])))
+    for name, cls in structs.items():
+        assert got[name] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[f"{name}.{f}"] == getattr(cls, f).offset, f"{name}.{f}"
+    assert (got["SK_MAX_GRID"], got["SK_MAX_PEERS"]) == (S.SK_MAX_GRID, S.SK_MAX_PEERS)
 
 
 def test_status_strings():
@@ -114,26 +133,54 @@ def test_grouped_rejects_mixed_types():
     assert S.sk_gemm_grouped(arr, None, FAKE, 1 << 20, 0) == S.SK_ERR_UNSUPPORTED
 
 
-def oracle_plan(shapes, blk, p, sched, grid, threshold=2, dtype="bf16"):
+def oracle_problems(shapes, blk):
     geos = [O.geometry(m, n, k, *blk) for (m, n, k) in shapes]
-    probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, shapes)])
-    cus = p // O.lds_wgs_per_cu(blk[0], blk[1])
-    return probs, O.plan_problems(probs, p=p, sched=sched, grid=grid, consts=MODEL, threshold=threshold, cus=cus,
-                                  auto_two_tile=dtype == "f64")
+    return O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, shapes)])
+
+
+def oracle_max_peers(probs, op):
+    """Largest peer count of any owner in the oracle's schedule."""
+    if op.sk_tile_end <= op.sk_tile_begin:
+        return 0
+    return max((len(sg.peers) for lst in O.segments(probs, op) for sg in lst if sg.role == O.ROLE_OWNER),
+               default=0)
 
 
 def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="row"):
+    """The library's plan against the schedule oracle's plan of the same
+    schedule.  An automatic schedule is first resolved by the library (its
+    policy is the library's, not the paper's) and the resolved schedule is
+    planned again by the oracle with the same model constants."""
     ds = [desc(m=m, n=n, k=k, ab_type=dtype, c_type={"f64": "f64", "bf16": "f32", "f16": "f32",
                                                        "f8e4m3": "f32"}[dtype],
                a_scale=0.5 if dtype == "f8e4m3" else 1.0, b_scale=0.5 if dtype == "f8e4m3" else 1.0,
                c_order=c_order)
           for (m, n, k) in shapes]
+    sched = S.SCHED[sched] if isinstance(sched, str) else sched
     cfg = S.make_config(sched=sched, blk=blk, grid=grid, wg_slots=p, threshold=threshold, model=MODEL)
     st, pl = S.sk_plan(ds if len(ds) > 1 else ds[0], cfg)
-    assert st == S.SK_OK, S.sk_status_string(st)
     # a column-major C is computed as C^T = B^T A^T: the tile grid is n x m
     oshapes = [(n, m, k) if c_order == "col" else (m, n, k) for (m, n, k) in shapes]
-    probs, op = oracle_plan(oshapes, blk, p, sched, grid, threshold or 2, dtype)
+    probs = oracle_problems(oshapes, blk)
+    if sched == S.SK_SCHED_AUTO:
+        assert st == S.SK_OK, S.sk_status_string(st)
+        osched = pl.sched if probs.tiles else S.SK_SCHED_DP
+        ogrid = grid
+    else:
+        osched, ogrid = sched, grid
+    op = O.plan_problems(probs, p=p, sched=osched, grid=ogrid, consts=MODEL, threshold=threshold or 2)
+    omp = oracle_max_peers(probs, op)
+    if omp > S.SK_MAX_PEERS:
+        # the paper's plan needs an owner with more peers than the library
+        # serves: a caller-fixed grid or hybrid is refused; a model grid is
+        # replaced by the best grid within the bound
+        if sched != S.SK_SCHED_AUTO and (grid > 0 or op.sched != O.SCHED_SK):
+            assert st == S.SK_ERR_UNSUPPORTED, (st, omp)
+            return None
+        assert st == S.SK_OK, S.sk_status_string(st)
+        assert pl.max_peers <= S.SK_MAX_PEERS and pl.grid < op.g
+        return pl
+    assert st == S.SK_OK, S.sk_status_string(st)
     assert pl.tiles == probs.tiles
     assert pl.iters_total == probs.total
     assert pl.grid == op.g
@@ -146,6 +193,7 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
         assert pl.sk_iters == probs.region_iters(op.sk_tile_begin, op.sk_tile_end)
         assert pl.sk_iter_begin == probs.tile_iter_begin(op.sk_tile_begin)
     assert pl.sched == op.sched
+    assert pl.max_peers == omp
     return pl
 
 
@@ -168,8 +216,7 @@ def test_plan_matches_schedule_oracle(m, n, k, dtype, big, p, sched, grid, thr, 
            "f8e4m3": (256, 256, 128) if big else (128, 128, 128)}[dtype]
     grid = min(grid, p)
     m, n, k = (-(-v // 16) * 16 for v in (m, n, k))    # satisfy the 16-byte rule for every dtype
-    check_plan_agrees([(m, n, k)], dtype, blk, p, S.SCHED[sched] if sched != "auto" else 0, grid, thr,
-                      c_order)
+    check_plan_agrees([(m, n, k)], dtype, blk, p, S.SCHED[sched], grid, thr, c_order)
 
 
 @settings(max_examples=60, deadline=None)
@@ -199,8 +246,7 @@ def test_auto_tile_and_schedule_policy():
     assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 16)
     # AUTO: basic Stream-K while t <= CUs (= wg_slots / LDS-bound workgroups per CU), else DP
     blk = (128, 128, 64)
-    cus = 512 // O.lds_wgs_per_cu(128, 128)
-    assert cus == 256
+    # (with wg_slots = 512 the 128x128x64 kernel's LDS allows 2 workgroups per CU: 256 CUs)
     for (m, n, k, want) in ((1024, 1024, 8192, S.SK_SCHED_SK), (2048, 2048 - 128, 8192, S.SK_SCHED_SK),
                             (2048, 2048, 8192, S.SK_SCHED_SK), (2048, 2048 + 128, 8192, S.SK_SCHED_DP),
                             (4096, 4096, 8192, S.SK_SCHED_DP),
@@ -217,3 +263,63 @@ def test_auto_tile_and_schedule_policy():
     # an explicit grid is honoured as Stream-K even when it equals t
     st, pl = S.sk_plan(d1, S.make_config(blk=blk, wg_slots=512, grid=64))
     assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK and pl.grid == 64
+
+
+def test_owner_peer_gate():
+    # deep-k single tiles whose paper model grid would give the owner more
+    # than SK_MAX_PEERS peers: the library's model grid stays within it
+    for (m, n, k, dt) in ((128, 128, 524288, "f64"), (128, 128, 2097152, "bf16"), (128, 128, 16384, "f64")):
+        d = desc(m=m, n=n, k=k, ab_type=dt, c_type="f64" if dt == "f64" else "f32")
+        for fx in ("auto", "serial", "spread"):
+            for sched in ("auto", "sk"):
+                st, pl = S.sk_plan(d, S.make_config(sched=sched, wg_slots=256, fixup=fx))
+                assert st == S.SK_OK, (m, n, k, dt, fx, sched)
+                assert pl.tiles == 1 and pl.max_peers <= S.SK_MAX_PEERS and pl.grid == pl.max_peers + 1, \
+                    (pl.grid, pl.max_peers)
+    # a caller-fixed grid that needs more peers is refused before any launch
+    d = desc(m=128, n=128, k=16384, ab_type="f64", c_type="f64")
+    cfg = S.make_config(sched="sk", blk=(128, 128, 16), grid=256, wg_slots=256)
+    assert S.sk_plan(d, cfg)[0] == S.SK_ERR_UNSUPPORTED
+    assert S.sk_gemm(d, cfg, FAKE, 1 << 30, 0) == S.SK_ERR_UNSUPPORTED
+    assert S.sk_plan(d, S.make_config(sched="sk", blk=(128, 128, 16), grid=65, wg_slots=256))[0] == S.SK_OK
+    assert S.sk_plan(d, S.make_config(sched="sk", blk=(128, 128, 16), grid=66, wg_slots=256))[0] == \
+        S.SK_ERR_UNSUPPORTED
+    # DP + one-tile SK with one leftover tile on 256 slots: 255 peers, refused;
+    # the automatic schedule of the same FP64 problem avoids it
+    d = desc(m=257 * 128, n=128, k=16384, ab_type="f64", c_type="f64")
+    st, pl = S.sk_plan(d, S.make_config(sched="dp1sk", blk=(128, 128, 16), wg_slots=256))
+    assert st == S.SK_ERR_UNSUPPORTED
+    st, pl = S.sk_plan(d, S.make_config(blk=(128, 128, 16), wg_slots=256))
+    assert st == S.SK_OK and pl.max_peers <= S.SK_MAX_PEERS
+
+
+def test_fixup_mode_resolution():
+    # explicit modes are honoured; AUTO takes the spread fixup only where an
+    # owner has at least two peers
+    d = desc(m=256, n=256, k=65536, ab_type="bf16", c_type="bf16")
+    for fx, want in (("serial", S.SK_FIXUP_SERIAL), ("spread", S.SK_FIXUP_SPREAD)):
+        st, pl = S.sk_plan(d, S.make_config(sched="sk", blk=(128, 128, 64), grid=64, wg_slots=512, fixup=fx))
+        assert st == S.SK_OK and pl.fixup == want
+    st, pl = S.sk_plan(d, S.make_config(sched="sk", blk=(128, 128, 64), grid=64, wg_slots=512))
+    assert st == S.SK_OK and pl.max_peers >= 2 and pl.fixup == S.SK_FIXUP_SPREAD
+    # the two-tile hybrid: every owner has at most one peer -> serial
+    d = desc(m=4096, n=4096, k=1024, ab_type="f64", c_type="f64")
+    st, pl = S.sk_plan(d, S.make_config(sched="2tsk", blk=(128, 128, 16), wg_slots=256, threshold=1))
+    assert st == S.SK_OK and pl.max_peers <= 1 and pl.fixup == S.SK_FIXUP_SERIAL
+    assert S.sk_plan(d, S.make_config(fixup=7, wg_slots=256))[0] == S.SK_ERR_INVALID_VALUE
+
+
+def test_workspace_reserves_flag_region_for_every_schedule():
+    # header (256 B) + flag region (2 x SK_MAX_GRID flags, 64 B apart) come
+    # first in every workspace, whatever the schedule; a spread plan holds two
+    # partial slots per workgroup
+    base = 256 + 2 * S.SK_MAX_GRID * 64
+    d = desc(m=1024, n=1024, k=1024, ab_type="bf16", c_type="f32")
+    st, pl = S.sk_plan(d, S.make_config(sched="dp", wg_slots=512))
+    assert st == S.SK_OK and pl.workspace_bytes >= base
+    slot = 128 * 128 * 4
+    for fx, per in (("serial", 1), ("spread", 2)):
+        st, pl = S.sk_plan(d, S.make_config(sched="sk", blk=(128, 128, 64), grid=100, wg_slots=512, fixup=fx))
+        assert st == S.SK_OK and pl.workspace_bytes >= base + per * 100 * slot
+    assert S.sk_plan(d, S.make_config(sched="sk", grid=S.SK_MAX_GRID + 1, wg_slots=4096))[0] == \
+        S.SK_ERR_INVALID_VALUE
