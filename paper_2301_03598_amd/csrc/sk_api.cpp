@@ -396,6 +396,13 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         pl->sched = sched == SK_SCHED_AUTO ? SK_SCHED_DP : sched;
         return SK_OK;
     }
+    if (c.iters == 0) {
+        // k == 0: no MAC-loop work; sk_gemm computes C = beta*C with its own
+        // kernel, so nothing persistent is planned
+        pl->sched = SK_SCHED_DP;
+        pl->dp_tiles = t;
+        return SK_OK;
+    }
     int p = 0;
     int cus = 0;
     if (sched != SK_SCHED_DP) {

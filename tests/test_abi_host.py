@@ -101,6 +101,14 @@ def test_validation_errors(kw, code):
     assert st == code
 
 
+def test_plan_of_k_zero():
+    # k == 0 (C = beta*C): planned without MAC-loop work, for every schedule
+    for sched in ("auto", "dp", "sk", "2tsk", "dp1sk"):
+        st, pl = S.sk_plan(desc(m=100, n=64, k=0), S.make_config(sched=sched, wg_slots=256))
+        assert st == S.SK_OK and pl.iters_total == 0 and pl.grid == 0, sched
+        assert S.sk_workspace_size(desc(m=100, n=64, k=0), S.make_config(sched=sched, wg_slots=256))[0] == S.SK_OK
+
+
 def test_noops_need_no_device():
     # m == 0 or n == 0: nothing to do, no pointers needed
     assert S.sk_gemm(desc(m=0, A=0, B=0, C=0), None, 0, 0, 0) == S.SK_OK
