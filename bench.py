@@ -89,6 +89,11 @@ class Sweep:
 class Runner:
     """Launches sk_gemm for every problem of a sweep on the current stream.
 
+    `cfg` is one configuration for every problem or a list with one per
+    problem; a problem whose plan the library refuses under it (an owner
+    would wait on more peers than the library serves) runs with the default
+    configuration instead and is counted in `fallbacks`.
+
     `step_timed` is the timed form: the launches grouped by kernel symbol
     (the problems of one symbol back to back -- the order of a sweep's
     independent GEMMs is free), one HIP event at each group boundary and no
@@ -102,22 +107,30 @@ class Runner:
         from paper_2301_03598_amd import streamk as S
         self.S = S
         self.sweep = sweep
-        self.cfg = cfg
+        n = len(sweep.shapes)
+        cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg] * n
         self.L = S.lib()
         need = 256
         self.plans = []
-        for i in range(len(sweep.shapes)):
-            st, pl = S.sk_plan(sweep.descs[i], cfg)
+        self.cfgs = []
+        self.fallbacks = 0
+        for i in range(n):
+            st, pl = S.sk_plan(sweep.descs[i], cfgs[i])
+            c = cfgs[i]
+            if st == S.SK_ERR_UNSUPPORTED:
+                c = S.make_config()
+                st, pl = S.sk_plan(sweep.descs[i], c)
+                self.fallbacks += 1
             S.check(st, "sk_plan")
             self.plans.append(pl)
+            self.cfgs.append(c)
             need = max(need, pl.workspace_bytes)
         self.ws = R.Workspace("cuda", need)
         self.stream = torch.cuda.current_stream()
         self.sptr = ctypes.c_void_p(self.stream.cuda_stream)
         self.wsp = ctypes.c_void_p(self.ws.ptr)
-        self.cfgp = ctypes.byref(cfg) if cfg is not None else None
-        self.dptrs = [ctypes.byref(sweep.descs[i]) for i in range(len(sweep.shapes))]
-        n = len(sweep.shapes)
+        self.cfgps = [ctypes.byref(c) if c is not None else None for c in self.cfgs]
+        self.dptrs = [ctypes.byref(sweep.descs[i]) for i in range(n)]
         self.ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
         self.ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
         # problems grouped by kernel symbol, in sweep order within a group
@@ -129,7 +142,7 @@ class Runner:
         self.group_steps = 0
 
     def _launch(self, i):
-        st = self.L.sk_gemm(self.dptrs[i], self.cfgp, self.wsp, self.ws.nbytes, self.sptr)
+        st = self.L.sk_gemm(self.dptrs[i], self.cfgps[i], self.wsp, self.ws.nbytes, self.sptr)
         if st != 0:
             raise RuntimeError(f"sk_gemm failed on problem {i}: {self.S.sk_status_string(st)}")
 
@@ -206,12 +219,15 @@ def kernel_of(pl, ab: str = "f16") -> str:
     return f"{kern}<{ab.upper()}, {pl.blk_m}x{pl.blk_n}x{pl.blk_k}, A k-contiguous, B n-contiguous>"
 
 
-def schedule_leg(sweep, sched, passes=2):
-    """Aggregate TFLOP/s of a sweep under one schedule (plain launches,
-    wall clock) and per-problem TFLOP/s from a separate event pass."""
+def schedule_leg(sweep, cfg, passes=2):
+    """Aggregate TFLOP/s of a sweep under one configuration (or one per
+    problem; plain launches, wall clock) and per-problem TFLOP/s from a
+    separate event pass."""
     import torch
     from paper_2301_03598_amd import streamk as S
-    run = Runner(sweep, S.make_config(sched=sched))
+    if isinstance(cfg, str):
+        cfg = S.make_config(sched=cfg)
+    run = Runner(sweep, cfg)
     run.step_plain()                # warm-up pass
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -223,14 +239,81 @@ def schedule_leg(sweep, sched, passes=2):
     run.step_events(durs)
     per = durs[0]
     tf = [sweep.flops[i] / (per[i] * 1e-3) / 1e12 for i in range(len(per))]
-    return {"tflops": round(sweep.total_flops / wall / 1e12, 2),
+    res = {"tflops": round(sweep.total_flops / wall / 1e12, 2),
+           "geomean_tflops": round(geomean(tf), 2),
+           "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}
+    if run.fallbacks:
+        res["fallbacks_to_default"] = run.fallbacks
+    return res, tf, run
+
+
+def fixed_split_configs(sweep, blk):
+    """Algorithm 4 (fixed split) as Stream-K with g = s t (section 4): per
+    problem, s is the largest divisor of the tile's iteration count I with
+    s t <= p (one wave on the resident slots) and s - 1 <= SK_MAX_PEERS, so
+    every tile is split into s equal k-ranges, one workgroup each."""
+    from paper_2301_03598_amd import streamk as S
+    out, splits = [], []
+    for (m, n, k), d in zip(sweep.shapes, sweep.descs):
+        st, pl = S.sk_plan(d, S.make_config(sched="sk", blk=blk))
+        S.check(st, "sk_plan")
+        t, p = pl.tiles, pl.wg_slots
+        I = -(-k // blk[2])
+        s = 1
+        for cand in range(1, min(I, S.SK_MAX_PEERS + 1) + 1):
+            if I % cand == 0 and cand * t <= p:
+                s = cand
+        splits.append(s)
+        out.append(S.make_config(sched="sk", blk=blk, grid=s * t))
+    return out, splits
+
+
+def ensemble_leg(sweep, tiles, passes=1):
+    """The idealized data-parallel ensemble (the paper's oracle column): per
+    problem the fastest of the library's data-parallel kernels over the given
+    tiles, by per-launch events; aggregate TFLOP/s from the summed best times."""
+    from paper_2301_03598_amd import streamk as S
+    best = None
+    for blk in tiles:
+        run = Runner(sweep, S.make_config(sched="dp", blk=blk))
+        run.step_plain()
+        durs = []
+        for _ in range(passes):
+            run.step_events(durs)
+        per = [min(d[i] for d in durs) for i in range(len(sweep.shapes))]
+        best = per if best is None else [min(a, b) for a, b in zip(best, per)]
+        del run
+    tf = [sweep.flops[i] / (best[i] * 1e-3) / 1e12 for i in range(len(best))]
+    tot_ms = sum(best)
+    return {"tflops": round(sweep.total_flops / (tot_ms * 1e-3) / 1e12, 2),
             "geomean_tflops": round(geomean(tf), 2),
-            "pct_peak": round(100 * sweep.total_flops / wall / 1e12 / PEAK_TFLOPS[sweep.ab], 2)}, tf, run
+            "tiles": [f"{b[0]}x{b[1]}x{b[2]}" for b in tiles],
+            "timing": "sum of per-launch event times of the best tile per problem"}, tf
+
+
+def attainable_tflops(m, n, k, in_b, out_b, peak_tflops):
+    """min(MFMA peak, arithmetic intensity x HBM bandwidth) of one GEMM, with
+    its compulsory bytes (A and B read once, C written once)."""
+    flops = 2.0 * m * n * k
+    bytes_ = (m * k + k * n) * in_b + m * n * out_b
+    return min(peak_tflops, flops / bytes_ * HBM_GBS / 1e3)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(budget_flops=7.0e11):
-    """The CPU oracle, as it stands, on a bounded sample of the sweep: the
-    problems in draw order whose flops fit the budget, FP16 inputs."""
+    """The CPU oracle, as it stands, on a bounded sample of the sweep (the
+    problems in draw order whose flops fit the budget, FP16 inputs), plus
+    configuration 1 (FP64 384x384x1024) and the precision set's
+    4096x1024x4096 on BF16 inputs, each timed once."""
     import oracle
     import workloads as W
     shapes = W.sweep_shapes()
@@ -247,10 +330,22 @@ def cpu_baseline(budget_flops=7.0e11):
         t0 = time.perf_counter()
         oracle.gemm(m, n, k, A, B, c_type="f32")
         t += time.perf_counter() - t0
+    extra = {}
+    for name, (m, n, k), ab, ct, dist, seed in (("config1_f64_384x384x1024", (384, 384, 1024), "f64", "f64",
+                                                  "uniform", 0),
+                                                 ("precision_c_bf16_4096x1024x4096", (4096, 1024, 4096), "bf16",
+                                                  "bf16", "normal", 2)):
+        A, B = W.gemm_operands(m, n, k, ab, seed, dist)
+        t0 = time.perf_counter()
+        oracle.gemm(m, n, k, A, B, c_type=ct)
+        dt = time.perf_counter() - t0
+        extra[name] = {"gflops": round(2.0 * m * n * k / dt / 1e9, 2), "s": round(dt, 3)}
     cores = int(os.environ.get("OMP_NUM_THREADS", 0) or len(os.sched_getaffinity(0)))
     return {"value": round(tot / t / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{len(pick)} sweep problems (draw order, FP16->FP32) fitting a "
-                      f"{budget_flops:.1e}-flop budget; {tot:.3e} flop in {t:.1f} s"}
+                      f"{budget_flops:.1e}-flop budget; {tot:.3e} flop in {t:.1f} s",
+            "configs": extra}
 
 
 def extended():
@@ -393,12 +488,23 @@ def grouped_leg(tune: bool = True):
         del keep
         return {"ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 1),
                 "sched": S.SCHED_NAME.get(plan.sched, plan.sched), "grid": plan.grid,
-                "tile": f"{plan.blk_m}x{plan.blk_n}x{plan.blk_k}", "label": label}
+                "tile": f"{plan.blk_m}x{plan.blk_n}x{plan.blk_k}", "fixup": S.FIXUP_NAME.get(plan.fixup),
+                "persistent": plan.sched != S.SK_SCHED_DP, "label": label}
+    # one persistent launch of the whole batch under each schedule
     out["grouped_default"] = grouped_time(S.make_config(sched="auto"), "library default")
+    out["grouped_sk_basic"] = grouped_time(S.make_config(sched="sk"), "basic Stream-K, model grid")
+    out["grouped_hybrid_2tile"] = grouped_time(S.make_config(sched="2tsk"), "two-tile SK + DP")
+    out["grouped_dp"] = grouped_time(S.make_config(sched="dp"), "data-parallel, one workgroup per tile")
+    base = T.paper_baseline("bf16")
+    out["grouped_paper_rule"] = grouped_time(base.config(), "paper rule: one tile, two-tile hybrid, model grid")
     if tune:
         tuner = T.Tuner()
         best = tuner.tune_grouped(descs, "bf16", "grouped512", reps=2)
         out["grouped_tuned"] = grouped_time(best.config(), "autotuned")
+        out["grouped_tuned"]["choice"] = {"sched": best.sched, "blk": list(best.blk), "grid": best.grid,
+                                          "threshold": best.threshold, "fixup": best.fixup}
+        out["speedup_tuned_vs_paper_rule"] = round(out["grouped_tuned"]["tflops"] /
+                                                   out["grouped_paper_rule"]["tflops"], 3)
     best_g = max(v["tflops"] for k, v in out.items() if k.startswith("grouped_"))
     out["speedup_grouped_vs_separate"] = round(best_g / out["separate_launches"]["tflops"], 3)
     del sw
@@ -406,7 +512,7 @@ def grouped_leg(tune: bool = True):
     return out
 
 
-def serving_leg(duration_s: float = 1.0, rate: float = 20000.0):
+def serving_leg(duration_s: float = 10.0, rate: float = 20000.0):
     """Poisson arrivals of mixed BF16/FP16 GEMMs (seed 4) through the
     continuous-batching server: p50/p99 latency and sustained TFLOP/s."""
     import torch
@@ -428,7 +534,11 @@ def serving_leg(duration_s: float = 1.0, rate: float = 20000.0):
            "offered_tflops": round(offered, 1), "sustained_tflops": round(st.sustained_tflops, 1),
            "makespan_s": round(st.makespan_s, 3), "p50_ms": round(st.p50_ms, 3),
            "p99_ms": round(st.p99_ms, 3), "launches": st.launches,
-           "mean_batch": round(st.mean_batch, 1), "max_queue": st.max_queue}
+           "mean_batch": round(st.mean_batch, 1), "max_queue": st.max_queue,
+           # requests queued or admitted but not launched, sampled every 10 ms:
+           # here once per 0.5 s of the run
+           "queue_depth_every_0.5s": st.queue_samples[::50],
+           "keeps_up_with_offered_load": bool(st.sustained_tflops >= 0.95 * offered)}
     del pools, srv
     torch.cuda.empty_cache()
     return res
@@ -513,17 +623,30 @@ def main():
     compare = {}
     if not args.no_compare:
         legs = {}
+        blk = (128, 128, 64)
         for name, sched in (("dp", "dp"), ("sk_basic", "sk"), ("hybrid_2tile", "2tsk"), ("dp_1tile_sk", "dp1sk")):
-            res, tf_leg, run_leg = schedule_leg(sweep, sched)
+            res, tf_leg, run_leg = schedule_leg(sweep, S.make_config(sched=sched, blk=blk))
             legs[name] = (res, tf_leg)
             del run_leg
+        # Algorithm 4 as Stream-K with g = s t
+        fs_cfgs, splits = fixed_split_configs(sweep, blk)
+        res, tf_leg, run_leg = schedule_leg(sweep, fs_cfgs)
+        res["split_histogram"] = {str(v): splits.count(v) for v in sorted(set(splits))}
+        legs["fixed_split"] = (res, tf_leg)
+        del run_leg
+        # the idealized data-parallel ensemble over the library's tiles
+        ens, tf_ens = ensemble_leg(sweep, [(256, 256, 64), (128, 128, 64), (64, 64, 64)])
+        legs["dp_ensemble"] = (ens, tf_ens)
         compare = {k: v[0] for k, v in legs.items()}
         compare["default"] = {"tflops": round(value, 2), "geomean_tflops": round(geomean(tf), 2),
                               "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2)}
+        compare["tile_of_schedule_legs"] = "128x128x64"
         tf_dp = legs["dp"][1]
-        for name, tfl in (("default", tf), ("sk_basic", legs["sk_basic"][1]), ("hybrid_2tile", legs["hybrid_2tile"][1]),
-                          ("dp_1tile_sk", legs["dp_1tile_sk"][1])):
+        for name, tfl in [("default", tf)] + [(k, v[1]) for k, v in legs.items() if k != "dp"]:
             compare[f"geomean_speedup_{name}_vs_dp"] = round(geomean([a / b for a, b in zip(tfl, tf_dp)]), 3)
+        for name, tfl in (("default", tf), ("sk_basic", legs["sk_basic"][1])):
+            compare[f"geomean_speedup_{name}_vs_dp_ensemble"] = \
+                round(geomean([a / b for a, b in zip(tfl, tf_ens)]), 3)
         compare["min_speedup_default_vs_dp"] = round(min(a / b for a, b in zip(tf, tf_dp)), 3)
         compare["max_speedup_default_vs_dp"] = round(max(a / b for a, b in zip(tf, tf_dp)), 3)
         log("compare:", compare)
@@ -536,8 +659,17 @@ def main():
     avg_flops = sum(sweep.flops[i] for i in idx) / len(idx)
     achieved = avg_flops / (avg_ms * 1e-3) / 1e12
     total_ms = sum(run.group_ms.values())
+    # the attainable rate of each of those launches, min(MFMA peak, AI x HBM
+    # bandwidth): most sweep problems sit below the ridge point, where the
+    # MFMA fraction alone understates how close a launch is to its bound
+    att_ms = sum(sweep.flops[i] / (attainable_tflops(*sweep.shapes[i], 2, 4, PEAK_TFLOPS["f16"]) * 1e12) * 1e3
+                 for i in idx)
+    below_ridge = sum(1 for i in idx if attainable_tflops(*sweep.shapes[i], 2, 4, PEAK_TFLOPS["f16"])
+                      < PEAK_TFLOPS["f16"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4),
+                "frac_of_attainable": round(att_ms / (avg_ms * len(idx)), 4),
+                "launches_below_ridge": f"{below_ridge} of {len(idx)} problems",
                 "traffic": measured_traffic(kname),
                 "kernel": kname, "launches": klaunch, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "avg_flops_per_launch": avg_flops, "time_share": round(run.group_ms[kname] / total_ms, 3),

@@ -96,7 +96,8 @@ typedef struct {
  *  sched            sk_sched_t.
  *  blk_m/n/k        tile shape; must be one built for the dtype.  Built:
  *                   F64 128x128x16 (default), 64x64x16; F16/BF16 256x256x64,
- *                   128x128x64; F8 256x256x128, 128x128x128.  F16/BF16/F8
+ *                   128x128x64, 64x64x64; F8 256x256x128, 128x128x128,
+ *                   64x64x128 (the 64x64 tiles only when asked for).  F16/BF16/F8
  *                   default: the 128x128 tile unless the problem has at least 8
  *                   full waves of those tiles (t >= 8 p), then the 256x256 tile.
  *                   AUTO's "CUs" is the device's CU count, or wg_slots divided

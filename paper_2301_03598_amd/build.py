@@ -54,10 +54,37 @@ def _compile(src: str, force: bool = True) -> str:
     return obj
 
 
+def sync_generated() -> int:
+    """Rewrite every generated kernel-instance unit (and the lookup table)
+    whose content differs from what gen_instances.py produces now, and
+    remove stale units; returns the number of files changed."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("gen_instances", os.path.join(CSRC, "gen_instances.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    want = gen.expected()
+    changed = 0
+    for f in os.listdir(CSRC):
+        if f.startswith("inst_") and f.endswith(".hip") and f not in want:
+            os.remove(os.path.join(CSRC, f))
+            changed += 1
+    for name, text in want.items():
+        path = os.path.join(CSRC, name)
+        if not os.path.exists(path) or open(path).read() != text:
+            with open(path, "w") as fh:
+                fh.write(text)
+            changed += 1
+    return changed
+
+
 def build(jobs: int = 0, verbose: bool = True, force: bool = True) -> str:
-    """Compile every unit (``force=False``: only those older than their
+    """Regenerate the instance units if they drifted from their generator,
+    compile every unit (``force=False``: only those older than their
     sources or headers) and link the library."""
     os.makedirs(BUILD_DIR, exist_ok=True)
+    n = sync_generated()
+    if verbose and n:
+        print(f"[build] {n} generated unit(s) rewritten from gen_instances.py", flush=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4)
     t0 = time.time()

@@ -26,17 +26,20 @@ struct TileDef {
 // moves half the operand bytes per flop, which wins once quantisation no
 // longer matters (FP8 8192^3: 1994 vs 1631 TFLOP/s row/row, 2300 vs 2086
 // row/col), while the 128x128 tile fills the machine on smaller problems.
+// The 64x64 tiles of the 16-bit and FP8 types are never the automatic
+// choice; they serve callers (and the autotuner) that pick them: a second,
+// smaller-tile kernel for problems too small or too memory-bound to fill
+// the machine with the larger tiles.
 const TileDef kF64Tiles[] = {{128, 128, 16}, {64, 64, 16}};
-const TileDef k16Tiles[] = {{256, 256, 64}, {128, 128, 64}};
-const TileDef kF8Tiles[] = {{256, 256, 128}, {128, 128, 128}};
+const TileDef k16Tiles[] = {{256, 256, 64}, {128, 128, 64}, {64, 64, 64}};
+const TileDef kF8Tiles[] = {{256, 256, 128}, {128, 128, 128}, {64, 64, 128}};
 
 const TileDef *tiles_for(int ab, int *n) {
-    *n = 2;
     switch (ab) {
-    case SK_F64: return kF64Tiles;
+    case SK_F64: *n = 2; return kF64Tiles;
     case SK_F16:
-    case SK_BF16: return k16Tiles;
-    case SK_F8_E4M3: return kF8Tiles;
+    case SK_BF16: *n = 3; return k16Tiles;
+    case SK_F8_E4M3: *n = 3; return kF8Tiles;
     }
     *n = 0;
     return nullptr;
@@ -55,6 +58,7 @@ struct Model {
 };
 
 Model default_model(int ab, int bm, bool spread) {
+    if (ab != SK_F64 && bm < 128) return spread ? Model{0.0, 6.0, 0.25, 0.02} : Model{0.0, 5.0, 0.25, 0.3};
     if (spread) {
         switch (ab) {
         case SK_F64: return bm >= 128 ? Model{15.6, 6.0, 2.03, 0.1} : Model{6.22, 2.6, 0.73, 0.05};

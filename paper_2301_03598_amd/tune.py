@@ -28,10 +28,16 @@ from . import runtime as R
 from . import streamk as S
 
 TILES = {"f64": [(128, 128, 16), (64, 64, 16)],
-         "f16": [(256, 256, 64), (128, 128, 64)],
-         "bf16": [(256, 256, 64), (128, 128, 64)],
-         "f8e4m3": [(256, 256, 128), (128, 128, 128)]}
+         "f16": [(256, 256, 64), (128, 128, 64), (64, 64, 64)],
+         "bf16": [(256, 256, 64), (128, 128, 64), (64, 64, 64)],
+         "f8e4m3": [(256, 256, 128), (128, 128, 128), (64, 64, 128)]}
 CTYPE = {"f64": "f64", "f16": "f32", "bf16": "f32", "f8e4m3": "f32"}
+
+# The paper's single configuration per precision (section 5.1, section 6):
+# the one tile that reaches near-peak on very large GEMMs (on MI355X the
+# largest built tile of each type), the two-tile SK + DP hybrid, and the
+# appendix A.1 model's grid wherever the hybrid reduces to basic Stream-K.
+PAPER_TILE = {ab: tiles[0] for ab, tiles in TILES.items()}
 
 
 @dataclass
@@ -41,9 +47,15 @@ class Choice:
     grid: int = 0
     threshold: int = 0
     us: float = 0.0
+    fixup: str = "auto"
 
     def config(self, **extra) -> S.sk_config_t:
-        return S.make_config(sched=self.sched, blk=self.blk, grid=self.grid, threshold=self.threshold, **extra)
+        return S.make_config(sched=self.sched, blk=self.blk, grid=self.grid, threshold=self.threshold,
+                             fixup=self.fixup, **extra)
+
+
+def paper_baseline(ab: str) -> Choice:
+    return Choice("2tsk", PAPER_TILE[ab])
 
 
 def _time_us(fn, reps: int = 5, warm: int = 2) -> float:
@@ -96,8 +108,9 @@ def measure(desc, cfg, ws: R.Workspace, reps: int = 5, grouped: bool = False) ->
 # ---------------------------------------------------------------------------
 
 def calibrate(ab: str, blk: Tuple[int, int, int], shapes: Sequence[Tuple[int, int, int]] = (),
-              grids: Sequence[int] = (), seed: int = 0) -> Dict[str, float]:
-    """Fit (a, b, c, d) in microseconds from basic-Stream-K timings."""
+              grids: Sequence[int] = (), seed: int = 0, fixup: str = "serial") -> Dict[str, float]:
+    """Fit (a, b, c, d) in microseconds from basic-Stream-K timings with the
+    given fixup (grids the library refuses are skipped)."""
     import numpy as np
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -113,7 +126,7 @@ def calibrate(ab: str, blk: Tuple[int, int, int], shapes: Sequence[Tuple[int, in
         I = -(-k // bk)
         gs = grids or sorted({g for g in (1, 2, 4, 8, 16, 32, 64, 128, 192, 256) if g <= T})
         for g in gs:
-            cfg = S.make_config(sched="sk", blk=blk, grid=g)
+            cfg = S.make_config(sched="sk", blk=blk, grid=g, fixup=fixup)
             us = measure(ops.desc, cfg, ws)
             if us is None:
                 continue
@@ -157,15 +170,19 @@ class Tuner:
 
     @staticmethod
     def candidates(ab: str, slots: Optional[Dict[Tuple[int, int, int], int]] = None) -> List[Choice]:
-        out = []
+        """The paper's configuration first, then tile x schedule x grid x
+        hybrid threshold x fixup."""
+        out = [paper_baseline(ab)]
         for blk in TILES[ab]:
             p = (slots or {}).get(blk, 256)
             out.append(Choice("dp", blk))
             out.append(Choice("auto", blk))
             out.append(Choice("dp1sk", blk))
             out.append(Choice("2tsk", blk, threshold=1))
-            for g in sorted({0, p // 4, p // 2, p}):
-                out.append(Choice("sk", blk, grid=g))
+            out.append(Choice("2tsk", blk))
+            for fx in ("serial", "spread"):
+                for g in sorted({0, p // 4, p // 2, p}):
+                    out.append(Choice("sk", blk, grid=g, fixup=fx))
         return out
 
     def _slots(self, ab: str, desc) -> Dict[Tuple[int, int, int], int]:
@@ -190,23 +207,23 @@ class Tuner:
         first = desc[0] if grouped else desc
         best: Optional[Choice] = None
         base_us = None
-        for ch in self.candidates(ab, self._slots(ab, first)):
+        for i, ch in enumerate(self.candidates(ab, self._slots(ab, first))):
             us = measure(desc, ch.config(), self.ws, reps, grouped)
-            if us is None:
+            if us is None:          # a plan the library refuses
                 continue
-            if ch.sched == "auto" and ch.blk == TILES[ab][0]:
-                base_us = us
+            if i == 0:
+                base_us = us        # the paper's configuration
             if best is None or us < best.us:
-                best = Choice(ch.sched, ch.blk, ch.grid, ch.threshold, us)
+                best = Choice(ch.sched, ch.blk, ch.grid, ch.threshold, us, ch.fixup)
         assert best is not None
-        self.table[key] = dict(asdict(best), baseline_us=base_us)
+        self.table[key] = dict(asdict(best), baseline_us=base_us, baseline=asdict(paper_baseline(ab)))
         return best
 
     def lookup(self, ab: str, m: int, n: int, k: int) -> Optional[Choice]:
         e = self.table.get(bucket(ab, m, n, k))
         if not e:
             return None
-        return Choice(e["sched"], tuple(e["blk"]), e["grid"], e["threshold"], e["us"])
+        return Choice(e["sched"], tuple(e["blk"]), e["grid"], e["threshold"], e["us"], e.get("fixup", "auto"))
 
     def config_for(self, ab: str, m: int, n: int, k: int) -> S.sk_config_t:
         ch = self.lookup(ab, m, n, k)
@@ -218,12 +235,12 @@ def main():
     import sys
     what = sys.argv[1] if len(sys.argv) > 1 else "calibrate"
     if what == "calibrate":
-        out = {}
-        for ab in ("f16", "bf16", "f8e4m3", "f64"):
+        dts = sys.argv[2].split(",") if len(sys.argv) > 2 else ["f16", "bf16", "f8e4m3", "f64"]
+        for ab in dts:
             for blk in TILES[ab]:
-                out[f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}"] = calibrate(ab, blk)
-                print(json.dumps({f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}": out[f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}"]}),
-                      flush=True)
+                for fx in ("serial", "spread"):
+                    key = f"{ab}:{blk[0]}x{blk[1]}x{blk[2]}:{fx}"
+                    print(json.dumps({key: calibrate(ab, blk, fixup=fx)}), flush=True)
     else:
         raise SystemExit(f"unknown command {what}")
 

@@ -212,16 +212,17 @@ def test_plan_config1_model_grid():
 
 @settings(max_examples=200, deadline=None)
 @given(m=st.integers(1, 9000), n=st.integers(1, 9000), k=st.integers(1, 9000),
-       dtype=st.sampled_from(["f64", "bf16", "f16", "f8e4m3"]), big=st.booleans(),
+       dtype=st.sampled_from(["f64", "bf16", "f16", "f8e4m3"]), ti=st.integers(0, 2),
        p=st.sampled_from([8, 64, 256, 512]),
        sched=st.sampled_from(["dp", "sk", "dp1sk", "2tsk", "auto"]),
        grid=st.integers(0, 64), thr=st.sampled_from([0, 1, 3]),
        c_order=st.sampled_from(["row", "col"]))
-def test_plan_matches_schedule_oracle(m, n, k, dtype, big, p, sched, grid, thr, c_order):
-    blk = {"f64": (128, 128, 16) if big else (64, 64, 16),
-           "bf16": (256, 256, 64) if big else (128, 128, 64),
-           "f16": (256, 256, 64) if big else (128, 128, 64),
-           "f8e4m3": (256, 256, 128) if big else (128, 128, 128)}[dtype]
+def test_plan_matches_schedule_oracle(m, n, k, dtype, ti, p, sched, grid, thr, c_order):
+    tiles = {"f64": [(128, 128, 16), (64, 64, 16)],
+             "bf16": [(256, 256, 64), (128, 128, 64), (64, 64, 64)],
+             "f16": [(256, 256, 64), (128, 128, 64), (64, 64, 64)],
+             "f8e4m3": [(256, 256, 128), (128, 128, 128), (64, 64, 128)]}[dtype]
+    blk = tiles[ti % len(tiles)]
     grid = min(grid, p)
     m, n, k = (-(-v // 16) * 16 for v in (m, n, k))    # satisfy the 16-byte rule for every dtype
     check_plan_agrees([(m, n, k)], dtype, blk, p, S.SCHED[sched], grid, thr, c_order)

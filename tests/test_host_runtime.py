@@ -59,4 +59,8 @@ def test_tuner_buckets():
     assert T.bucket("f64", 128, 8192, 3000) == "f64:7:13:12"
     cands = T.Tuner.candidates("bf16", {(256, 256, 64): 256, (128, 128, 64): 512})
     assert any(c.sched == "dp" for c in cands) and any(c.sched == "sk" and c.grid == 512 for c in cands)
-    assert {c.blk for c in cands} == {(256, 256, 64), (128, 128, 64)}
+    assert {c.blk for c in cands} == {(256, 256, 64), (128, 128, 64), (64, 64, 64)}
+    # the paper's configuration comes first: one tile per precision, the
+    # two-tile hybrid, the model's grid
+    assert (cands[0].sched, cands[0].blk, cands[0].grid) == ("2tsk", (256, 256, 64), 0)
+    assert {c.fixup for c in cands if c.sched == "sk"} == {"serial", "spread"}
