@@ -184,27 +184,48 @@ typedef struct {
     int32_t max_peers;        /* largest peer count of any tile's owner */
 } sk_plan_t;
 
-/* Plan the call without launching it.  d points to `count` descriptors
- * (count == 1 for sk_gemm).  Pure host computation. */
+/* Plan the call without launching it: the schedule (sections 3.2, 4, 5.2),
+ * the grid (appendix A.1 model), the Stream-K region and the fixup.  d points
+ * to `count` descriptors (count == 1 for sk_gemm).  Pure host computation;
+ * the device is only queried for its CU count when cfg->wg_slots is 0. */
 sk_status_t sk_plan(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg,
                     sk_plan_t *out);
 
 /* Workspace bytes needed by sk_gemm (count == 1) or sk_gemm_grouped with the
- * same descriptors and configuration.  The workspace is device memory owned
- * by the caller; it must be zero-filled before its first use, and every call
- * that completes leaves its flag region zeroed again.  One workspace serves
- * one call in flight at a time. */
+ * same descriptors and configuration: the header and the fixed flag region,
+ * then (Stream-K schedules only) the partial-tile slots of Algorithm 5's
+ * StorePartials -- one BM x BN accumulator tile per workgroup, two with the
+ * SPREAD fixup -- then the grouped call's descriptor and problem tables.
+ * The workspace is device memory owned by the caller; it must be
+ * zero-filled before its first use.  Flags are raised with a per-call epoch
+ * and never cleared, so a completed call leaves the workspace ready for the
+ * next one without any reset.  One workspace serves one call in flight at a
+ * time; calls that overlap on one workspace race.
+ * Errors: SK_ERR_INVALID_VALUE (bytes NULL, or a descriptor rejected as by
+ * sk_gemm), SK_ERR_UNSUPPORTED (no such kernel, or a plan whose owner would
+ * wait on more than SK_MAX_PEERS peers). */
 sk_status_t sk_workspace_size(const sk_gemm_desc_t *d, int32_t count,
                               const sk_config_t *cfg, size_t *bytes);
 
-/* One GEMM, enqueued on `stream`.  cfg may be NULL. */
+/* One GEMM (section 2: C = alpha A B + beta C), enqueued on `stream` as one
+ * kernel launch of the plan sk_plan returns: data-parallel tiles
+ * (Algorithm 2), basic Stream-K (Algorithm 5, the grid from the appendix A.1
+ * model unless cfg->grid is set) or a section 5.2 hybrid.  A, B, C are
+ * device pointers owned by the caller; `workspace` (ws_bytes >= what
+ * sk_workspace_size returns) holds the partial tiles and flags.  cfg may be
+ * NULL.  All validation happens before anything is enqueued: on any status
+ * other than SK_OK nothing was launched and C is untouched. */
 sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg,
                     void *workspace, size_t ws_bytes, void *stream);
 
 /* `count` independent GEMMs with the same ab_type, c_type and orders but any
  * shapes, pointers, alpha, beta and scales, in one persistent launch whose
  * Stream-K iteration space is the concatenation of the problems' spaces
- * (problem index outermost).  d is host memory; it is copied into the
+ * (problem index outermost): section 4's even split of the MAC-loop
+ * iterations applied to the union of the problems' tiles, each problem's
+ * tiles linearised m -> n -> k as for one GEMM.  Problems with m, n or k
+ * equal to zero contribute no tiles (k == 0 or alpha == 0: C = beta C).
+ * Validation and errors as sk_gemm; a count < 1 is SK_ERR_INVALID_VALUE.  d is host memory; it is copied into the
  * workspace stream-ordered, so it must stay valid until the stream reaches
  * this call (pinned memory is required under stream capture, and replays of
  * a captured call read d again: shapes must then be unchanged). */
@@ -212,11 +233,15 @@ sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count,
                             const sk_config_t *cfg, void *workspace,
                             size_t ws_bytes, void *stream);
 
-/* Synchronise `stream`, read the workspace's error word and clear it.
- * Returns SK_ERR_TIMEOUT if a fixup wait gave up since the last check. */
+/* Synchronise `stream` and read the workspace's error word.  Returns
+ * SK_ERR_TIMEOUT if a fixup wait (Algorithm 5's Wait, bounded here in real
+ * time) gave up since the last check; the header and the flag region are
+ * then reset to the zero-filled state, so the workspace can be used again.
+ * SK_ERR_INVALID_VALUE for a NULL or undersized workspace. */
 sk_status_t sk_workspace_check(void *workspace, size_t ws_bytes, void *stream);
 
-/* Static text for a status code. */
+/* Static text for a status code (never NULL; unknown codes get a generic
+ * text). */
 const char *sk_status_string(sk_status_t s);
 
 #ifdef __cplusplus
