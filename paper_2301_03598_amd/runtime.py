@@ -11,8 +11,9 @@ from . import streamk as S
 
 
 class Workspace:
-    """Zero-filled device bytes for one call in flight at a time (the
-    library leaves the flag region zeroed after every completed call)."""
+    """Zero-filled device bytes for one call in flight at a time.  The
+    library raises its flags with a per-call epoch and never needs them
+    cleared, so a completed call leaves the workspace ready for the next."""
 
     def __init__(self, device="cuda", nbytes: int = 0):
         self.device = torch.device(device)
