@@ -264,7 +264,9 @@ def fixed_split_configs(sweep, blk):
             if I % cand == 0 and cand * t <= p:
                 s = cand
         splits.append(s)
-        out.append(S.make_config(sched="sk", blk=blk, grid=s * t))
+        # s = 1 (the tiles alone fill the slots, or I has no divisor that
+        # fits): no split, the data-parallel schedule of the same tile
+        out.append(S.make_config(sched="sk", blk=blk, grid=s * t) if s > 1 else S.make_config(sched="dp", blk=blk))
     return out, splits
 
 

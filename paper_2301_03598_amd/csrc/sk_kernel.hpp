@@ -166,13 +166,28 @@ __device__ __forceinline__ uint32_t lds_off(uint32_t row, uint32_t chunk) {
 // fragment reads -- 16-bit transpose reads: 4 consecutive k-rows x 32 bytes
 // per 16 lanes; 8-bit: 8 consecutive k-rows x 16 bytes; FP64: 4 k-rows two
 // apart x 128 bytes -- hit every bank once per 256 bytes.  A k-row of 256
-// bytes fills the 64 banks; one of 128 bytes shares them with its neighbour.
+// bytes fills the 64 banks; one of 128 (64) bytes shares them with 1 (3)
+// neighbours.  The swizzled chunk stays inside its k-row: the value is below
+// the k-row's chunk count (ROWS * E / 16).
 template <int E, int ROWS>
 __device__ __forceinline__ int nkc_swizzle(int p) {
-    if constexpr (E == 8) return 8 * ((p >> 1) & 1);
-    else if constexpr (E == 2) return 4 * (p & 3);
-    else if constexpr (ROWS * E >= 256) return 2 * (p & 7);
-    else return 2 * ((p >> 1) & 3);
+    constexpr int RB = ROWS * E;     // bytes per k-row
+    static_assert(RB >= 64, "at least four chunks per k-row");
+    if constexpr (E == 8) {
+        static_assert(RB >= 256, "FP64 swizzle needs 16 chunks");
+        return 8 * ((p >> 1) & 1);
+    } else if constexpr (E == 2) {
+        // 256-byte k-rows: the 4 k-rows of a read share the banks;
+        // 128-byte k-rows: k-rows p and p + 2 do
+        if constexpr (RB >= 256) return 4 * (p & 3);
+        else return 2 * ((p >> 1) & 1);
+    } else {
+        // 8 consecutive k-rows per read: 256-byte k-rows all share the banks,
+        // 128-byte ones in fours, 64-byte ones in pairs (p and p + 4)
+        if constexpr (RB >= 256) return 2 * (p & 7);
+        else if constexpr (RB == 128) return 2 * ((p >> 1) & 3);
+        else return 2 * ((p >> 2) & 1);
+    }
 }
 
 template <class C, int ROWS, bool KC>
@@ -324,7 +339,7 @@ __device__ __forceinline__ u32x4 frag_tr(const char *op, uint32_t base, int ks, 
     const int g = lane >> 4, s16 = lane & 15;
     const uint32_t r0 = base + 16 * (g & 1) + 4 * (s16 & 3);
     const uint32_t p = (uint32_t)(ks * 16 + 8 * (g >> 1) + (s16 >> 2));
-    const uint32_t off = p * RB + ((((r0 >> 3) ^ (4u * (s16 >> 2)))) << 4) + (r0 & 7) * 2;
+    const uint32_t off = p * RB + (((r0 >> 3) ^ (uint32_t)nkc_swizzle<2, ROWS>((int)p)) << 4) + (r0 & 7) * 2;
     const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)(op + off));
     const s16x4 hi =
         __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)(op + off + 4 * RB));

@@ -48,15 +48,23 @@ def test_spread_integer_exact_with_trace(ab, ct, big, ws):
 @pytest.mark.parametrize("sched,grid,slots", [("sk", 37, 0), ("sk", 0, 0), ("dp1sk", 0, 24), ("2tsk", 0, 8)])
 def test_spread_equals_serial_bitwise(ab, ct, sched, grid, slots, ws):
     blk = SMALL_TILE[ab]
-    m, n, k = 5 * blk[0] - 24, 3 * blk[1] + 40, 24 * blk[2] + 16
+    m, n, k = 5 * blk[0] - 24, 3 * blk[1] + 48, 24 * blk[2] + 16
     dist = "uniform" if ab in ("f64", "f16") else "normal"
     A, B = operands(m, n, k, ab, 7, dist)
-    bits = []
-    for fx in ("serial", "spread"):
-        cfg = S.make_config(sched=sched, blk=blk, grid=grid, wg_slots=slots, fixup=fx)
-        say(f"spread-vs-serial {ab}->{ct} {sched} grid={grid} slots={slots} fixup={fx}")
+    bits, plans = [], []
+    # the model's grid depends on the fixup (its constants differ), so the
+    # serial run takes the grid the spread plan resolved: same segments,
+    # same partial sums, same order of additions
+    for fx in ("spread", "serial"):
+        g = plans[0].grid if plans else grid
+        cfg = S.make_config(sched=sched, blk=blk, grid=g, wg_slots=slots, fixup=fx)
+        say(f"spread-vs-serial {ab}->{ct} {sched} grid={g} slots={slots} fixup={fx}")
         Ct, plan, _ = run_gemm(m, n, k, dev(A), dev(B), c_type=ct, cfg=cfg, ws=ws)
         bits.append(c_bits(Ct, m, n, "row"))
+        plans.append(plan)
+    assert [(p.sched, p.grid, p.sk_tile_begin, p.sk_tile_end) for p in plans[:1]] == \
+        [(p.sched, p.grid, p.sk_tile_begin, p.sk_tile_end) for p in plans[1:]]
+    assert plans[1].fixup == S.SK_FIXUP_SERIAL
     assert np.array_equal(bits[0], bits[1])
     # and within the bound against the oracle
     check_case(m, n, k, ab, ct, dist=dist, seed=7, cfg=S.make_config(sched=sched, blk=blk, grid=grid,

@@ -28,6 +28,8 @@ SMALL_TILE = {"f64": (64, 64, 16), "f16": (128, 128, 64), "bf16": (128, 128, 64)
               "f8e4m3": (128, 128, 128)}
 BIG_TILE = {"f64": (128, 128, 16), "f16": (256, 256, 64), "bf16": (256, 256, 64),
             "f8e4m3": (256, 256, 128)}
+# the third tile of the 16-bit and FP8 types (FP64's small tile is 64x64)
+TINY_TILE = {"f16": (64, 64, 64), "bf16": (64, 64, 64), "f8e4m3": (64, 64, 128)}
 
 
 @pytest.fixture(scope="module")
@@ -117,7 +119,7 @@ RAGGED = (208, 336, 400)     # not multiples of any tile; multiples of 16
 def test_dtypes_layouts_integer_exact(ab, ct, layout, sched, ws):
     ao, bo, co = layout.split("/")
     m, n, k = RAGGED
-    for blk in (SMALL_TILE[ab], BIG_TILE[ab]):
+    for blk in (SMALL_TILE[ab], BIG_TILE[ab]) + ((TINY_TILE[ab],) if ab in TINY_TILE else ()):
         cfg = S.make_config(sched=sched, blk=blk, grid=0 if sched == "dp" else 7)
         check_case(m, n, k, ab, ct, dist="int4", a_order=ao, b_order=bo, c_order=co, cfg=cfg, ws=ws)
 
@@ -129,6 +131,10 @@ def test_dtypes_real_valued_bound(ab, ct, ws):
     for sched in ("dp", "sk", "auto"):
         cfg = S.make_config(sched=sched, blk=SMALL_TILE[ab])
         check_case(m, n, k, ab, ct, dist=dist, cfg=cfg, ws=ws, seed=5)
+    if ab in TINY_TILE:
+        for sched in ("dp", "sk"):
+            cfg = S.make_config(sched=sched, blk=TINY_TILE[ab])
+            check_case(m, n, k, ab, ct, dist=dist, cfg=cfg, ws=ws, seed=5)
 
 
 @pytest.mark.parametrize("ab,ct", [("f64", "f64"), ("bf16", "f32"), ("f16", "f16"), ("f8e4m3", "bf16")])
