@@ -218,6 +218,28 @@ sk_status_t sk_workspace_size(const sk_gemm_desc_t *d, int32_t count,
 sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/* Bytes of the device scratch array behind sk_gemm_noalloc: one copy on
+ * every GPU the library runs on, held until the process ends. */
+#define SK_NOALLOC_SCRATCH_BYTES (80u << 20)
+
+/* sk_gemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same plan, kernels and results as sk_gemm with the same d and cfg, but the
+ * workspace is the library's fixed scratch array on the current device
+ * (SK_NOALLOC_SCRATCH_BYTES).  Nothing is allocated by this call or by the
+ * library on its behalf.  A plan whose workspace (sk_workspace_size) exceeds
+ * the array is rejected with SK_ERR_WORKSPACE_TOO_SMALL before anything is
+ * enqueued (choose a smaller grid, the SERIAL fixup or the DP schedule).
+ * The first call on a device also enqueues, on `stream`, the zeroing of the
+ * array's header and flag region.  Every call on one GPU shares its array:
+ * calls that overlap on one GPU (on different streams, or from several host
+ * threads without ordering) race and give undefined results.
+ * wait_error: optional device int32 (NULL = not reported) into which the
+ * kernels OR 1 if a fixup wait gave up (the call's results are then
+ * undefined); the caller zeroes it. */
+sk_status_t sk_gemm_noalloc(const sk_gemm_desc_t *d, const sk_config_t *cfg,
+                            int32_t *wait_error, void *stream);
+
 /* `count` independent GEMMs with the same ab_type, c_type and orders but any
  * shapes, pointers, alpha, beta and scales, in one persistent launch whose
  * Stream-K iteration space is the concatenation of the problems' spaces

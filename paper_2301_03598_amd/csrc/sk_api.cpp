@@ -625,6 +625,7 @@ Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws
     P.wait_ticks = wait_ticks(cfg);
     char *w = (char *)ws;
     P.hdr = (int32_t *)w;
+    P.err = P.hdr + HDR_ERR;
     P.flags = (int32_t *)(w + WS_HEADER);
     if (L.partials) P.partials = w + L.partials;
     if (cfg && cfg->trace) {
@@ -671,8 +672,14 @@ sk_status_t sk_workspace_size(const sk_gemm_desc_t *d, int32_t count, const sk_c
     return SK_OK;
 }
 
-sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *workspace, size_t ws_bytes,
-                    void *stream) {
+}  // extern "C"
+
+namespace {
+
+// sk_gemm's body.  err: the error word a giving-up fixup wait sets (NULL:
+// the workspace header's).
+sk_status_t gemm_on(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *workspace, size_t ws_bytes,
+                    int32_t *err, void *stream) {
     if (!d) return SK_ERR_INVALID_VALUE;
     sk_status_t s = validate(*d);
     if (s != SK_OK) return s;
@@ -694,7 +701,75 @@ sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *works
     KernelEntry e = find_kernel(key);
     if (!e.launch) return SK_ERR_UNSUPPORTED;
     Params P = make_params(c, pl, L, workspace, cfg);
+    if (err) P.err = err;
     return e.launch(P, pl.grid, stream) == (int)hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace that needs no allocation: a fixed device array, one copy per GPU
+// the library runs on, kept until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (on the host it is only a stand-in
+// for the symbol); it uses the per-device address hipGetSymbolAddress gives.
+// ---------------------------------------------------------------------------
+static_assert(SK_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) char scratch[SK_NOALLOC_SCRATCH_BYTES];
+
+// Header words and flag region of a fresh workspace: zeroed by a kernel (a
+// memset node would not be safe under stream capture).
+__global__ void zero_words_kernel(int32_t *w, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device; the first call on a device
+// looks it up and enqueues the zeroing of its header and flag region on
+// `stream` (stream order puts it before the caller's launch).
+sk_status_t scratch_for_current_device(void *stream, void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SK_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SK_ERR_HIP;
+        const int words = (WS_HEADER + FLAG_REGION) / 4;
+        hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                           (int32_t *)ptr, words);
+        if (hipGetLastError() != hipSuccess) return SK_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sk_status_t sk_gemm(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *workspace, size_t ws_bytes,
+                    void *stream) {
+    return gemm_on(d, cfg, workspace, ws_bytes, nullptr, stream);
+}
+
+sk_status_t sk_gemm_noalloc(const sk_gemm_desc_t *d, const sk_config_t *cfg, int32_t *wait_error, void *stream) {
+    if (!d) return SK_ERR_INVALID_VALUE;
+    sk_status_t s = validate(*d);
+    if (s != SK_OK) return s;
+    if (d->m == 0 || d->n == 0) return SK_OK;
+    // C = beta C needs no workspace
+    if (d->k == 0 || d->alpha == 0.0) return gemm_on(d, cfg, nullptr, 0, wait_error, stream);
+    // the plan's workspace must fit the scratch array (checked before the
+    // device is touched)
+    size_t need = 0;
+    s = sk_workspace_size(d, 1, cfg, &need);
+    if (s != SK_OK) return s;
+    if (need > (size_t)SK_NOALLOC_SCRATCH_BYTES) return SK_ERR_WORKSPACE_TOO_SMALL;
+    void *ws = nullptr;
+    s = scratch_for_current_device(stream, &ws);
+    if (s != SK_OK) return s;
+    return gemm_on(d, cfg, ws, (size_t)SK_NOALLOC_SCRATCH_BYTES, wait_error, stream);
 }
 
 sk_status_t sk_gemm_grouped(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, void *workspace,

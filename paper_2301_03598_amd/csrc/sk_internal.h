@@ -94,6 +94,7 @@ struct Params {
     void *partials;          // partial-tile slots of BM*BN accumulators (see slot_first / slot_last)
     int32_t *flags;          // the fixed flag region, FLAG_STRIDE ints apart
     int32_t *hdr;            // workspace header: HDR_ERR, HDR_GEN, HDR_DONE
+    int32_t *err;            // error word a giving-up wait sets (hdr + HDR_ERR unless the caller gives one)
     int32_t *trace;          // optional segment trace
     int64_t trace_cap;
 };

@@ -1400,7 +1400,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
             red_l[1] = last;
             continue;
         }
-        if (!ended) wait_flags(p.flags, x + 1, last, -1, x + 1, epoch, p.hdr + HDR_ERR, p.wait_ticks, tid);
+        if (!ended) wait_flags(p.flags, x + 1, last, -1, x + 1, epoch, p.err, p.wait_ticks, tid);
         // peers' partial tiles are added in ascending slot order inside the
         // epilogue, fragment by fragment
         store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last, lds0, lds1);
@@ -1413,7 +1413,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
             for (int u = 0; u < 2; ++u) {
                 if (red_tile[u] < 0) continue;
                 const int f = red_f[u], l = red_l[u];
-                wait_flags(p.flags, f, l, x, MAX_GRID + f, epoch, p.hdr + HDR_ERR, p.wait_ticks, tid0);
+                wait_flags(p.flags, f, l, x, MAX_GRID + f, epoch, p.err, p.wait_ticks, tid0);
                 const TileRef tr = tile_of_tile<C::GROUPED>(p, red_tile[u]);
                 const Problem P = uniform_problem(*tr.P);
                 int tm, tn;

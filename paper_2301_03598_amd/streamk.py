@@ -33,7 +33,9 @@ SCHED = {"auto": SK_SCHED_AUTO, "dp": SK_SCHED_DP, "sk": SK_SCHED_SK,
          "dp1sk": SK_SCHED_DP_1TILE_SK, "2tsk": SK_SCHED_2TILE_SK_DP}
 SCHED_NAME = {v: k for k, v in SCHED.items()}
 
-EXPORTS = ["sk_plan", "sk_workspace_size", "sk_gemm", "sk_gemm_grouped",
+SK_NOALLOC_SCRATCH_BYTES = 80 << 20
+
+EXPORTS = ["sk_plan", "sk_workspace_size", "sk_gemm", "sk_gemm_noalloc", "sk_gemm_grouped",
            "sk_workspace_check", "sk_status_string"]
 
 
@@ -94,6 +96,7 @@ def lib():
         L.sk_workspace_size.argtypes = [P(sk_gemm_desc_t), c_int32, P(sk_config_t),
                                         P(ctypes.c_size_t)]
         L.sk_gemm.argtypes = [P(sk_gemm_desc_t), P(sk_config_t), c_void_p, ctypes.c_size_t, c_void_p]
+        L.sk_gemm_noalloc.argtypes = [P(sk_gemm_desc_t), P(sk_config_t), c_void_p, c_void_p]
         L.sk_gemm_grouped.argtypes = [P(sk_gemm_desc_t), c_int32, P(sk_config_t), c_void_p,
                                       ctypes.c_size_t, c_void_p]
         L.sk_workspace_check.argtypes = [c_void_p, ctypes.c_size_t, c_void_p]
@@ -132,6 +135,11 @@ def sk_workspace_size(descs, cfg=None):
 def sk_gemm(desc, cfg, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
     return lib().sk_gemm(ctypes.byref(desc), _cfg_ptr(cfg), c_void_p(workspace_ptr or None),
                          ws_bytes, c_void_p(stream or None))
+
+
+def sk_gemm_noalloc(desc, cfg, wait_error_ptr: int, stream: int) -> int:
+    return lib().sk_gemm_noalloc(ctypes.byref(desc), _cfg_ptr(cfg), c_void_p(wait_error_ptr or None),
+                                 c_void_p(stream or None))
 
 
 def sk_gemm_grouped(descs, cfg, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
