@@ -298,6 +298,20 @@ struct Call {
         }
         return best;
     }
+    // Whether no tile's owner has more than `lim` peers when [0, n) is split
+    // evenly over g workgroups.  Ranges are q or q + 1 iterations long
+    // (q = n / g), so a tile of I iterations meets at most ceil((I - 1) / q)
+    // ranges after its first, and the longest tile at least
+    // ceil(imax / (q + 1)) ranges in all; the exact O(g) count is only
+    // needed between the two bounds.
+    bool peers_within(int64_t n, int64_t g, int64_t lim) const {
+        if (n <= 0 || g <= 1) return true;
+        const int64_t q = n / g;
+        if (q <= 0) return max_peers(0, n, g) <= lim;
+        if ((imax - 1 + q - 1) / q <= lim) return true;
+        if ((imax + q) / (q + 1) - 1 > lim) return false;
+        return max_peers(0, n, g) <= lim;
+    }
 };
 
 sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, bool grouped,
@@ -428,7 +442,7 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     auto sk_grid = [&](bool spread, double *val) {
         const Model &m = spread ? m_spread : m_serial;
         const int g = model_grid(c.iters, c.imax, pg, m,
-                                 [&](int gg) { return c.max_peers(0, c.iters, gg) <= SK_MAX_PEERS; });
+                                 [&](int gg) { return c.peers_within(c.iters, gg, SK_MAX_PEERS); });
         if (val) *val = model_time(c.iters, c.imax, g, m);
         return g;
     };
@@ -525,6 +539,16 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     if (!model_g) {
         fix = fix_req == SK_FIXUP_AUTO ? (mp >= kSpreadMinPeers ? SK_FIXUP_SPREAD : SK_FIXUP_SERIAL) : fix_req;
     }
+    // Deep-k basic Stream-K (every tile split over at least 8 workgroups):
+    // the hardware's round-robin placement (workgroup x on XCD x mod 8) puts
+    // the workgroups that run the same k-range of different tiles on one
+    // XCD, whose L2 then serves the A and B k-slices those tiles share;
+    // contiguous runs per XCD would give each XCD whole tiles at unrelated
+    // k offsets.  Measured (BF16, 128x128 tiles, spread fixup): 256x256x65536
+    // 34.8 -> 31.4 us, 512x512x32768 45.3 -> 34.7, 1024x1024x16384 56.3 ->
+    // 48.1; with two workgroups per tile (4096x1024x4096) the contiguous
+    // runs stay faster (45.2 vs 51.3).
+    if (pl->xcd_remap && sched == SK_SCHED_SK && ske > skb && g >= 8 * (ske - skb)) pl->xcd_remap = 0;
     pl->sched = sched;
     pl->grid = (int32_t)g;
     pl->dp_first = sched == SK_SCHED_DP_1TILE_SK ? 1 : 0;
@@ -535,6 +559,69 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     pl->dp_tiles = t - (ske - skb);
     pl->fixup = fix;
     pl->max_peers = (int32_t)mp;
+    return SK_OK;
+}
+
+// Plans of single GEMMs, cached by everything planning reads (device,
+// shape, types, orders, leading dimensions and the configuration fields that
+// steer the plan), so a shape seen before is launched without re-planning.
+struct PlanKey {
+    int32_t dev;
+    int32_t ab, ct, ao, bo, co;
+    int64_t m, n, k, lda, ldb, ldc;
+    sk_config_t cfg;       // trace, trace_capacity and wait_limit_us zeroed
+    int32_t has_cfg;
+};
+
+constexpr size_t kPlanCacheSize = 64;
+std::mutex g_plan_mu;
+std::vector<std::pair<PlanKey, sk_plan_t>> g_plan_cache;
+size_t g_plan_next = 0;
+
+bool plan_key(const sk_gemm_desc_t &d, const sk_config_t *cfg, PlanKey *k) {
+    std::memset(k, 0, sizeof(*k));
+    if (hipGetDevice(&k->dev) != hipSuccess) return false;
+    k->ab = d.ab_type; k->ct = d.c_type;
+    k->ao = d.a_order; k->bo = d.b_order; k->co = d.c_order;
+    k->m = d.m; k->n = d.n; k->k = d.k;
+    k->lda = d.lda; k->ldb = d.ldb; k->ldc = d.ldc;
+    if (cfg) {
+        k->has_cfg = 1;
+        k->cfg.sched = cfg->sched;
+        k->cfg.blk_m = cfg->blk_m; k->cfg.blk_n = cfg->blk_n; k->cfg.blk_k = cfg->blk_k;
+        k->cfg.grid = cfg->grid;
+        k->cfg.wg_slots = cfg->wg_slots;
+        k->cfg.sk_threshold_waves = cfg->sk_threshold_waves;
+        k->cfg.flags = cfg->flags;
+        k->cfg.model_a = cfg->model_a; k->cfg.model_b = cfg->model_b;
+        k->cfg.model_c = cfg->model_c; k->cfg.model_d = cfg->model_d;
+        k->cfg.fixup = cfg->fixup;
+        k->cfg.model_bw = cfg->model_bw;
+    }
+    return true;
+}
+
+// plan_call for one GEMM, through the cache
+sk_status_t plan_single(const Call &c, const sk_gemm_desc_t &d, const sk_config_t *cfg, sk_plan_t *pl) {
+    PlanKey key;
+    const bool keyed = plan_key(d, cfg, &key);
+    if (keyed) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (const auto &e : g_plan_cache)
+            if (std::memcmp(&e.first, &key, sizeof(key)) == 0) {
+                *pl = e.second;
+                return SK_OK;
+            }
+    }
+    sk_status_t s = plan_call(c, cfg, pl);
+    if (s != SK_OK || !keyed) return s;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plan_cache.size() < kPlanCacheSize) {
+        g_plan_cache.push_back({key, *pl});
+    } else {
+        g_plan_cache[g_plan_next] = {key, *pl};
+        g_plan_next = (g_plan_next + 1) % kPlanCacheSize;
+    }
     return SK_OK;
 }
 
@@ -657,7 +744,7 @@ sk_status_t sk_plan(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *c
     Call c;
     sk_status_t s = build_call(d, count, cfg, count > 1, &c);
     if (s != SK_OK) return s;
-    s = plan_call(c, cfg, out);
+    s = count == 1 ? plan_single(c, d[0], cfg, out) : plan_call(c, cfg, out);
     if (s != SK_OK) return s;
     out->workspace_bytes = layout_for(*out, d[0].ab_type, count).total;
     return SK_OK;
@@ -692,7 +779,7 @@ sk_status_t gemm_on(const sk_gemm_desc_t *d, const sk_config_t *cfg, void *works
     s = build_call(d, 1, cfg, false, &c);
     if (s != SK_OK) return s;
     sk_plan_t pl;
-    s = plan_call(c, cfg, &pl);
+    s = plan_single(c, *d, cfg, &pl);
     if (s != SK_OK) return s;
     Layout L = layout_for(pl, d->ab_type, 1);
     if (!workspace || ws_bytes < L.total) return SK_ERR_WORKSPACE_TOO_SMALL;

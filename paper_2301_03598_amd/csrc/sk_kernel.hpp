@@ -1087,55 +1087,32 @@ struct Spread {
         return (u == 0 ? b.b0 : u == 1 ? b.b1 : b.b2) + o;
     }
 
-    // Elements of chunk c (16 bytes of the thread-fragment order) of tile
+    // Element e of chunk c (16 bytes of the thread-fragment order) of tile
     // (tm, tn): alpha * v (+ beta * C), rounded once, masked at the edges.
     template <int CT>
-    __device__ static __forceinline__ void put_chunk(const Problem &P, int tm, int tn, int c, const u32x4 &raw) {
+    __device__ static __forceinline__ void put_elem(const Problem &P, int tm, int tn, int c, int e,
+                                                    typename C::Acc v) {
         using Acc = typename C::Acc;
         using PL = PartialLayout<C>;
         constexpr int EB = CBytes<CT>::v;
         const int t = c % THREADS, vi = c / THREADS;
         const int sc = vi % PL::CPF, fij = vi / PL::CPF, fi = fij / C::FN, fj = fij % C::FN;
         const int lane = t & 63, wave = t >> 6, wm = wave >> 1, wn = wave & 1;
-        const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
-        const bool rd = P.beta != 0.0;
+        int row, col;
         if constexpr (C::MT == 16) {
             // FP64: the chunk holds rows 4(2 sc) + lane/16 and 4(2 sc + 1) + lane/16 of one column
-            const f64x2 v = __builtin_bit_cast(f64x2, raw);
-            const int col = tn * C::BN + wn * C::WTN + fj * 16 + (lane & 15);
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int row = tm * C::BM + wm * C::WTM + fi * 16 + 4 * (2 * sc + e) + (lane >> 4);
-                if (row < P.m && col < P.n) {
-                    char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
-                    Acc w = alpha * v[e];
-                    if (rd) w = w + beta * load_c<CT, Acc>(q);
-                    put_c<CT, Acc>(q, w);
-                }
-            }
+            row = tm * C::BM + wm * C::WTM + fi * 16 + 4 * (2 * sc + e) + (lane >> 4);
+            col = tn * C::BN + wn * C::WTN + fj * 16 + (lane & 15);
         } else {
             // 32x32 blocks: four consecutive columns of one row
-            const f32x4 v = __builtin_bit_cast(f32x4, raw);
-            const int row = tm * C::BM + wm * C::WTM + fi * C::MT + (lane % C::MT);
-            const int col = tn * C::BN + wn * C::WTN + fj * C::MT + 8 * sc + 4 * (lane / C::MT);
-            char *rp = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
-            Acc a[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = alpha * v[e];
-            const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
-            if (P.c_vec && interior) {
-                put4<CT, Acc>(rp, a, beta, rd);
-            } else if (row < P.m) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (col + e < P.n) {
-                        char *q = rp + e * EB;
-                        Acc w = a[e];
-                        if (rd) w = w + beta * load_c<CT, Acc>(q);
-                        put_c<CT, Acc>(q, w);
-                    }
-                }
-            }
+            row = tm * C::BM + wm * C::WTM + fi * C::MT + (lane % C::MT);
+            col = tn * C::BN + wn * C::WTN + fj * C::MT + 8 * sc + 4 * (lane / C::MT) + e;
+        }
+        if (row < P.m && col < P.n) {
+            char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+            Acc w = (Acc)P.alpha * v;
+            if (P.beta != 0.0) w = w + (Acc)P.beta * load_c<CT, Acc>(q);
+            put_c<CT, Acc>(q, w);
         }
     }
 
@@ -1165,24 +1142,29 @@ struct Spread {
             }
             wait_dma();
             __syncthreads();
-            for (int j = tid; j < n; j += THREADS) {
-                u32x4 raw;
-                if constexpr (sizeof(typename C::Acc) == 4) {
-                    f32x4 v = *(const f32x4 *)(blk(bufs, j / 64) + (j % 64) * 16);
-                    for (int cc = 1; cc < s; ++cc) {
-                        const int k = cc * pc + j;
-                        v = v + *(const f32x4 *)(blk(bufs, k / 64) + (k % 64) * 16);
-                    }
-                    raw = __builtin_bit_cast(u32x4, v);
-                } else {
-                    f64x2 v = *(const f64x2 *)(blk(bufs, j / 64) + (j % 64) * 16);
-                    for (int cc = 1; cc < s; ++cc) {
-                        const int k = cc * pc + j;
-                        v = v + *(const f64x2 *)(blk(bufs, k / 64) + (k % 64) * 16);
-                    }
-                    raw = __builtin_bit_cast(u32x4, v);
+            // one element per thread (the order of additions is per element,
+            // so the elements of a chunk need not share a thread); the
+            // contributors' values are read eight at a time ahead of their
+            // additions, which stay in ascending order
+            using Acc = typename C::Acc;
+            constexpr int EPC = 16 / (int)sizeof(Acc);
+            for (int u = tid; u < n * EPC; u += THREADS) {
+                const int j = u / EPC, e = u % EPC;
+                auto at = [&](int cc) -> Acc {
+                    const int k = cc * pc + j;
+                    return *(const Acc *)(blk(bufs, k / 64) + (k % 64) * 16 + e * (int)sizeof(Acc));
+                };
+                Acc v = at(0);
+                int cc = 1;
+                for (; cc + 8 <= s; cc += 8) {
+                    Acc t[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) t[i] = at(cc + i);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v = v + t[i];
                 }
-                put_chunk<CT>(P, tm, tn, cp + j, raw);
+                for (; cc < s; ++cc) v = v + at(cc);
+                put_elem<CT>(P, tm, tn, cp + j, e, v);
             }
         }
         __syncthreads();                                       // LDS free for the next user
