@@ -6,9 +6,9 @@
 
 namespace sk {
 
-template <Dt D, int BM, int BN, bool A, bool B, bool G>
+template <Dt D, int BM, int BN, bool A, bool B, bool G, int NW = 4>
 KernelEntry entry(bool dp_only) {
-    using C = Cfg<D, BM, BN, A, B, G>;
+    using C = Cfg<D, BM, BN, A, B, G, NW>;
     return dp_only ? KernelEntry{launch_dp<C>, occupancy_sk<C>}
                    : KernelEntry{launch_sk<C>, occupancy_sk<C>};
 }

@@ -87,10 +87,17 @@ template <> struct DtTraits<Dt::F8> {
     using Frag = f32x16;
 };
 
-template <Dt D, int BM_, int BN_, bool AKC_, bool BKC_, bool GROUPED_>
+template <Dt D, int BM_, int BN_, bool AKC_, bool BKC_, bool GROUPED_, int NW_ = 4>
 struct Cfg {
     static constexpr Dt DT = D;
     static constexpr bool AKC = AKC_, BKC = BKC_, GROUPED = GROUPED_;
+    // waves per workgroup, arranged 2 (along m) x NW/2 (along n); each wave
+    // instruction of LDS-DMA staging moves 1 KiB, so one round of all waves
+    // moves NW KiB
+    static constexpr int NW = NW_, THREADS = 64 * NW_;
+    static constexpr int WGM = 2, WGN = NW_ / 2;
+    static constexpr int DMA_ROUND = 1024 * NW_;
+    static_assert(NW_ == 4 || NW_ == 8, "four or eight waves");
     static constexpr int E = DtTraits<D>::E;
     static constexpr int VEC = 16 / E;          // elements per 16-byte load
     static constexpr int BK = 8 * VEC;          // MAC-loop iteration: 128 bytes of k
@@ -101,7 +108,7 @@ struct Cfg {
     static constexpr int KROW = 128;
     static constexpr int BKS = KROW / E;        // k per staged k-tile
     static constexpr int SUB = BK / BKS;        // staged k-tiles per MAC-loop iteration
-    static constexpr int WTM = BM / 2, WTN = BN / 2;   // 2 x 2 waves
+    static constexpr int WTM = BM / WGM, WTN = BN / WGN;   // the wave's block of C
     static constexpr int MT = DtTraits<D>::MT;
     static constexpr int FM = WTM / MT, FN = WTN / MT;
     static constexpr int FRAG_N = DtTraits<D>::FRAG_N;
@@ -113,14 +120,14 @@ struct Cfg {
     // room).
     static constexpr int NSTAGE = D == Dt::F64 ? 3 : (KROW == 64 ? 4 : 2);
     static constexpr int LDS = NSTAGE * STAGE;
-    static constexpr int DMA_PER_KTILE = STAGE / 4096;   // LDS-DMA loads per wave per staged k-tile
+    static constexpr int DMA_PER_KTILE = STAGE / DMA_ROUND;   // LDS-DMA loads per wave per staged k-tile
     // k-tile instruction order pinned for the scheduler (MFMAs interleaved
     // with the loads and fragment reads, barrier before the last k-step):
     // measured faster for the 16-bit 256x256 tile (one workgroup, so one
     // wave, per SIMD) and for FP8; slower for the 16-bit 128x128 tile (two
     // workgroups per CU cover each other's stalls) and FP64, which keep the
     // compiler's order
-    static constexpr bool ORDERED = D == Dt::F8 || (E == 2 && BM >= 256);
+    static constexpr bool ORDERED = NW == 4 && (D == Dt::F8 || (E == 2 && BM >= 256));
     // the first fixup peer is staged through LDS (not for the 256x256 FP8
     // tile, whose transpose-read fragments leave no registers for it)
     static constexpr bool FIX_LDS = !(D == Dt::F8 && BM >= 256);
@@ -132,7 +139,7 @@ struct Cfg {
     static constexpr int ACC_N = FM * FN * FRAG_N;     // accumulators per thread
     static constexpr int ACC_CHUNKS = ACC_N * (int)sizeof(Acc) / 16;
     static constexpr int SLOT_BYTES = BM * BN * (int)sizeof(Acc);
-    static_assert(BM * BN == THREADS * ACC_N, "accumulator split");
+    static_assert(BM * BN == THREADS * ACC_N && FM >= 1 && FN >= 1, "accumulator split");
 };
 
 // LDS byte offset of 16-byte chunk c of row r (KROW-byte rows, XOR
@@ -193,7 +200,8 @@ __device__ __forceinline__ int nkc_swizzle(int p) {
 template <class C, int ROWS, bool KC>
 struct StageDma {
     static constexpr int E = C::E, VEC = C::VEC, BK = C::BKS, KROW = C::KROW;
-    static constexpr int NL = ROWS * KROW / 4096;   // loads per wave per staged k-tile
+    static constexpr int NW = C::NW;
+    static constexpr int NL = ROWS * KROW / C::DMA_ROUND;   // loads per wave per staged k-tile
     static constexpr int RPB = 1024 / KROW;         // KC: rows per 1 KiB block
     static constexpr int LPR = KROW / 16;           // KC: lanes per row
     static constexpr int CPR = ROWS * E / 16;       // !KC: chunks per k-row
@@ -219,10 +227,10 @@ struct StageDma {
             const int c = (L % LPR) ^ key;
             ub = p + (int64_t)row0 * ld * E;
             ustep = (int64_t)BK * E;
-            ustride = (uint32_t)(4 * RPB * ld * E);
+            ustride = (uint32_t)(NW * RPB * ld * E);
             voff = (uint32_t)(((int64_t)rr * ld + c * VEC) * E);
             const int rem = rows_total - row0 - rr;
-            rows_valid = rem <= 0 ? 0 : (rem + 4 * RPB - 1) / (4 * RPB);
+            rows_valid = rem <= 0 ? 0 : (rem + NW * RPB - 1) / (NW * RPB);
             kofs = c * VEC;
             lds_w = (uint32_t)(w * 1024);
         } else {
@@ -230,7 +238,7 @@ struct StageDma {
             const int c = (L % CPR) ^ nkc_swizzle<E, ROWS>(pr);
             ub = p + (int64_t)row0 * E;
             ustep = (int64_t)BK * ld * E;
-            ustride = (uint32_t)(4 * KR * ld * E);
+            ustride = (uint32_t)(NW * KR * ld * E);
             voff = (uint32_t)(((int64_t)pr * ld + c * VEC) * E);
             mn_valid = row0 + c * VEC < rows_total;
             kofs = pr;
@@ -251,7 +259,7 @@ struct StageDma {
     __device__ __forceinline__ void issue(char *lds, int kt, int K, bool live, bool interior) const {
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void *)(ub + kt * ustep), (short)0, 0x7fffffff, 0x00020000);
-        constexpr int BLK = 4096;                       // LDS bytes between a wave's blocks
+        constexpr int BLK = C::DMA_ROUND;               // LDS bytes between a wave's blocks
         if (!C::ORDERED && live && interior) {
 #pragma unroll
             for (int i = 0; i < NL; ++i) dma(rs, lds + lds_w + i * BLK, voff, i * ustride);
@@ -264,7 +272,7 @@ struct StageDma {
             const int k0 = kt * BK + kofs;
 #pragma unroll
             for (int i = 0; i < NL; ++i)
-                dma(rs, lds + lds_w + i * BLK, (live && (interior || (mn_valid && k0 + i * 4 * KR < K))) ? voff : OOB,
+                dma(rs, lds + lds_w + i * BLK, (live && (interior || (mn_valid && k0 + i * NW * KR < K))) ? voff : OOB,
                     i * ustride);
         }
     }
@@ -602,7 +610,7 @@ __device__ __forceinline__ void mac_loop(const Problem &P, int tm, int tn, int i
         return;
     }
     static_assert(Frag<C>::NSUB % 2 == 0, "fragment double buffer needs an even step count");
-    const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+    const int lane = tid & 63, wave = tid >> 6, wm = wave / C::WGN, wn = wave % C::WGN;
     const int q = C::MT == 16 ? (lane >> 4) : (lane >> 5);
     const uint32_t arow = (uint32_t)(wm * C::WTM + (lane % C::MT));
     const uint32_t brow = (uint32_t)(wn * C::WTN + (lane % C::MT));
@@ -734,7 +742,7 @@ struct PartialLayout {
     static constexpr int PER = 16 / (int)sizeof(typename C::Acc);   // accumulators per chunk
     static constexpr int CPF = C::FRAG_N / PER;                      // chunks per fragment
     __device__ static __forceinline__ int64_t off(int i, int j, int s, int tid) {
-        return ((int64_t)((i * C::FN + j) * CPF + s) * THREADS + tid) * 16;
+        return ((int64_t)((i * C::FN + j) * CPF + s) * C::THREADS + tid) * 16;
     }
 };
 
@@ -807,7 +815,8 @@ struct FixStage {
     static constexpr int VPH = C::ACC_CHUNKS / PH;                    // chunks per thread per phase
     static constexpr int H = VPH / 2;                                 // chunks per buffer
     static constexpr int ROWS_PH = C::FM / PH;                        // fragment rows per phase
-    static_assert(H * 4096 <= C::STAGE && C::FM % PH == 0 && VPH % 2 == 0, "fixup staging fits the LDS");
+    static constexpr int RB = C::DMA_ROUND;                           // bytes of one chunk of every thread
+    static_assert(H * RB <= C::STAGE && C::FM % PH == 0 && VPH % 2 == 0, "fixup staging fits the LDS");
 
     // stage chunks [ph*VPH, (ph+1)*VPH) of the slot
     __device__ static __forceinline__ void issue(const char *slot, char *lds0, char *lds1, int ph, int tid) {
@@ -815,9 +824,9 @@ struct FixStage {
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
         for (int u = 0; u < VPH; ++u) {
-            char *dst = (u < H ? lds0 : lds1) + (u % H) * 4096 + w * 1024;
+            char *dst = (u < H ? lds0 : lds1) + (u % H) * RB + w * 1024;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16,
-                                                     (uint32_t)tid * 16u, (uint32_t)((ph * VPH + u) * 4096), 0,
+                                                     (uint32_t)tid * 16u, (uint32_t)((ph * VPH + u) * RB), 0,
                                                      CPOL_DEVICE);
         }
     }
@@ -830,7 +839,7 @@ struct FixStage {
 #pragma unroll
         for (int s = 0; s < PL::CPF; ++s) {
             const int u = (i * C::FN + j) * PL::CPF + s - (i / ROWS_PH) * VPH;
-            c[s] = *(const u32x4 *)((u < H ? lds0 : lds1) + (u % H) * 4096 + tid * 16);
+            c[s] = *(const u32x4 *)((u < H ? lds0 : lds1) + (u % H) * RB + tid * 16);
         }
         if constexpr (PL::PER == 4) {
             const f32x8 lo = __builtin_shufflevector(__builtin_bit_cast(f32x4, c[0]), __builtin_bit_cast(f32x4, c[1]),
@@ -890,7 +899,7 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
     using Acc = typename C::Acc;
     constexpr int EB = CBytes<CT>::v;
     constexpr int G = C::FRAG_N / 4;                 // column groups per fragment
-    const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+    const int lane = tid & 63, wave = tid >> 6, wm = wave / C::WGN, wn = wave % C::WGN;
     const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
     const bool rd = P.beta != 0.0;
     const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
@@ -1087,6 +1096,58 @@ struct Spread {
         return (u == 0 ? b.b0 : u == 1 ? b.b1 : b.b2) + o;
     }
 
+    // Elements of chunk c (16 bytes of the thread-fragment order) of tile
+    // (tm, tn): alpha * v (+ beta * C), rounded once, masked at the edges.
+    template <int CT>
+    __device__ static __forceinline__ void put_chunk(const Problem &P, int tm, int tn, int c, const u32x4 &raw) {
+        using Acc = typename C::Acc;
+        using PL = PartialLayout<C>;
+        constexpr int EB = CBytes<CT>::v;
+        const int t = c % C::THREADS, vi = c / C::THREADS;
+        const int sc = vi % PL::CPF, fij = vi / PL::CPF, fi = fij / C::FN, fj = fij % C::FN;
+        const int lane = t & 63, wave = t >> 6, wm = wave / C::WGN, wn = wave % C::WGN;
+        const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
+        const bool rd = P.beta != 0.0;
+        if constexpr (C::MT == 16) {
+            // FP64: the chunk holds rows 4(2 sc) + lane/16 and 4(2 sc + 1) + lane/16 of one column
+            const f64x2 v = __builtin_bit_cast(f64x2, raw);
+            const int col = tn * C::BN + wn * C::WTN + fj * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int row = tm * C::BM + wm * C::WTM + fi * 16 + 4 * (2 * sc + e) + (lane >> 4);
+                if (row < P.m && col < P.n) {
+                    char *q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+                    Acc w = alpha * v[e];
+                    if (rd) w = w + beta * load_c<CT, Acc>(q);
+                    put_c<CT, Acc>(q, w);
+                }
+            }
+        } else {
+            // 32x32 blocks: four consecutive columns of one row
+            const f32x4 v = __builtin_bit_cast(f32x4, raw);
+            const int row = tm * C::BM + wm * C::WTM + fi * C::MT + (lane % C::MT);
+            const int col = tn * C::BN + wn * C::WTN + fj * C::MT + 8 * sc + 4 * (lane / C::MT);
+            char *rp = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+            Acc a[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[e] = alpha * v[e];
+            const bool interior = (tm + 1) * C::BM <= P.m && (tn + 1) * C::BN <= P.n;
+            if (P.c_vec && interior) {
+                put4<CT, Acc>(rp, a, beta, rd);
+            } else if (row < P.m) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (col + e < P.n) {
+                        char *q = rp + e * EB;
+                        Acc w = a[e];
+                        if (rd) w = w + beta * load_c<CT, Acc>(q);
+                        put_c<CT, Acc>(q, w);
+                    }
+                }
+            }
+        }
+    }
+
     // Element e of chunk c (16 bytes of the thread-fragment order) of tile
     // (tm, tn): alpha * v (+ beta * C), rounded once, masked at the edges.
     template <int CT>
@@ -1095,9 +1156,9 @@ struct Spread {
         using Acc = typename C::Acc;
         using PL = PartialLayout<C>;
         constexpr int EB = CBytes<CT>::v;
-        const int t = c % THREADS, vi = c / THREADS;
+        const int t = c % C::THREADS, vi = c / C::THREADS;
         const int sc = vi % PL::CPF, fij = vi / PL::CPF, fi = fij / C::FN, fj = fij % C::FN;
-        const int lane = t & 63, wave = t >> 6, wm = wave >> 1, wn = wave & 1;
+        const int lane = t & 63, wave = t >> 6, wm = wave / C::WGN, wn = wave % C::WGN;
         int row, col;
         if constexpr (C::MT == 16) {
             // FP64: the chunk holds rows 4(2 sc) + lane/16 and 4(2 sc + 1) + lane/16 of one column
@@ -1130,7 +1191,7 @@ struct Spread {
             const int n = c1 - cp < pc ? c1 - cp : pc;         // chunks this pass
             const int nblk = (s * pc + 63) / 64;              // 1 KiB staging blocks
             __syncthreads();                                   // LDS free (MAC loop / previous pass)
-            for (int b = w; b < nblk; b += 4) {
+            for (int b = w; b < nblk; b += C::NW) {
                 const int k = b * 64 + L;                      // staging index: contributor k / pc, chunk k % pc
                 const int cc = k / pc, j = k % pc;
                 const int slot = cc == 0 ? p.g + f : f + cc;   // the owner's is its last-segment slot
@@ -1142,13 +1203,38 @@ struct Spread {
             }
             wait_dma();
             __syncthreads();
-            // one element per thread (the order of additions is per element,
-            // so the elements of a chunk need not share a thread); the
-            // contributors' values are read eight at a time ahead of their
-            // additions, which stay in ascending order
             using Acc = typename C::Acc;
             constexpr int EPC = 16 / (int)sizeof(Acc);
-            for (int u = tid; u < n * EPC; u += THREADS) {
+            if (n >= C::THREADS) {
+                // enough chunks for every thread: one 16-byte chunk per
+                // thread, vector reads and stores
+                for (int j = tid; j < n; j += C::THREADS) {
+                    u32x4 raw;
+                    if constexpr (sizeof(Acc) == 4) {
+                        f32x4 v = *(const f32x4 *)(blk(bufs, j / 64) + (j % 64) * 16);
+                        for (int cc = 1; cc < s; ++cc) {
+                            const int k = cc * pc + j;
+                            v = v + *(const f32x4 *)(blk(bufs, k / 64) + (k % 64) * 16);
+                        }
+                        raw = __builtin_bit_cast(u32x4, v);
+                    } else {
+                        f64x2 v = *(const f64x2 *)(blk(bufs, j / 64) + (j % 64) * 16);
+                        for (int cc = 1; cc < s; ++cc) {
+                            const int k = cc * pc + j;
+                            v = v + *(const f64x2 *)(blk(bufs, k / 64) + (k % 64) * 16);
+                        }
+                        raw = __builtin_bit_cast(u32x4, v);
+                    }
+                    put_chunk<CT>(P, tm, tn, cp + j, raw);
+                }
+                continue;
+            }
+            // a short slice over many contributors: one element per thread
+            // (the order of additions is per element, so the elements of a
+            // chunk need not share a thread), the contributors' values read
+            // eight at a time ahead of their additions, which stay in
+            // ascending order
+            for (int u = tid; u < n * EPC; u += C::THREADS) {
                 const int j = u / EPC, e = u % EPC;
                 auto at = [&](int cc) -> Acc {
                     const int k = cc * pc + j;
@@ -1419,30 +1505,30 @@ __device__ __forceinline__ void sk_body(const Params &p) {
 }
 
 template <class C>
-__global__ __launch_bounds__(THREADS) void sk_kernel(Params p) {
+__global__ __launch_bounds__(C::THREADS) void sk_kernel(Params p) {
     sk_body<C, false>(p);
 }
 
 template <class C>
-__global__ __launch_bounds__(THREADS) void dp_kernel(Params p) {
+__global__ __launch_bounds__(C::THREADS) void dp_kernel(Params p) {
     sk_body<C, true>(p);
 }
 
 template <class C>
 int launch_sk(const Params &p, int grid, void *stream) {
-    hipLaunchKernelGGL(sk_kernel<C>, dim3(grid), dim3(THREADS), 0, (hipStream_t)stream, p);
+    hipLaunchKernelGGL(sk_kernel<C>, dim3(grid), dim3(C::THREADS), 0, (hipStream_t)stream, p);
     return (int)hipGetLastError();
 }
 
 template <class C>
 int launch_dp(const Params &p, int grid, void *stream) {
-    hipLaunchKernelGGL(dp_kernel<C>, dim3(grid), dim3(THREADS), 0, (hipStream_t)stream, p);
+    hipLaunchKernelGGL(dp_kernel<C>, dim3(grid), dim3(C::THREADS), 0, (hipStream_t)stream, p);
     return (int)hipGetLastError();
 }
 
 template <class C>
 int occupancy_sk(int *blocks) {
-    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sk_kernel<C>, THREADS, 0);
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sk_kernel<C>, C::THREADS, 0);
 }
 
 }  // namespace sk
