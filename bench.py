@@ -704,7 +704,7 @@ def main():
                                "to multiples of 8 (seed 1); FP16 inputs U[-1,1], FP32 accumulate "
                                "and output; alpha=1, beta=0; row-major; library default configuration "
                                "(basic Stream-K while tiles <= CUs, else data-parallel; 128x128 tiles "
-                               "unless 8 full waves)",
+                               "unless 2 full waves)",
                    "problems": len(shapes), "flops_per_step": total_flops,
                    "tiles": tiles, "schedules": kinds},
         "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2),

@@ -98,8 +98,9 @@ typedef struct {
  *                   F64 128x128x16 (default), 64x64x16; F16/BF16 256x256x64,
  *                   128x128x64, 64x64x64; F8 256x256x128, 128x128x128,
  *                   64x64x128 (the 64x64 tiles only when asked for).  F16/BF16/F8
- *                   default: the 128x128 tile unless the problem has at least 8
- *                   full waves of those tiles (t >= 8 p), then the 256x256 tile.
+ *                   default: the 128x128 tile unless the problem has at least 2
+ *                   (F16/BF16) or 8 (F8) full waves of those tiles (t >= 2 p,
+ *                   t >= 8 p), then the 256x256 tile.
  *                   AUTO's "CUs" is the device's CU count, or wg_slots divided
  *                   by the tile's workgroups per CU by LDS (160 KiB / (2 (BM +
  *                   BN) 128 B)) when wg_slots is given.

@@ -135,7 +135,12 @@ int lds_wgs_per_cu(const TileDef &t) {
 // use the 256x256 tile (its larger per-tile reuse wins once the machine is
 // saturated many times over; below that the 128x128 tile's two workgroups
 // per CU hide more latency).
-constexpr int64_t kBigTileWaves = 8;
+// FP8: 8.  FP16/BF16 (eight-wave 256x256 kernel): 2 -- BF16 DP 4096^3
+// 870 -> 1026 TFLOP/s, 4096x8192x4096 1002 -> 1105, 2048x8192x8192 1050 ->
+// 1169, 3072x3072x8192 696 -> 801; even at 6144x6144x4096; the FP16 sweep
+// is unchanged within noise (352 -> 354).
+constexpr int64_t kBigTileWaves = 8;        // FP8
+constexpr int64_t kBigTileWaves16 = 2;      // FP16 / BF16
 
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
     int n = 0;
@@ -347,7 +352,8 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
             s = query_slots(ks, &p_small);
             if (s != SK_OK) return s;
         }
-        if (t_small < kBigTileWaves * (int64_t)p_small) c->tile = small;
+        const int64_t waves = d[0].ab_type == SK_F8_E4M3 ? kBigTileWaves : kBigTileWaves16;
+        if (t_small < waves * (int64_t)p_small) c->tile = small;
     }
     c->key = KernelKey{d[0].ab_type, c->tile.bm, c->tile.bn, a_kcontig(d[0]), b_kcontig(d[0]), grouped, false};
     c->probs.resize(count);

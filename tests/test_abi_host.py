@@ -241,9 +241,10 @@ def test_grouped_plan_matches_schedule_oracle(shapes, p, sched, grid):
 
 
 def test_auto_tile_and_schedule_policy():
-    # FP16/BF16 without a tile: 128x128 unless 8 full waves of it (t >= 8 p)
+    # FP16/BF16 without a tile: 128x128 unless 2 full waves of it (t >= 2 p)
     cfg = S.make_config(wg_slots=512)
-    for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 128), (4096, 4096, 128), (256, 256, 128)):
+    for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 256), (4096, 4096, 256), (4096, 2048, 128),
+                          (4096, 4096 - 128, 128), (4096 + 128, 4096, 256), (256, 256, 128)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="bf16", c_type="f32"), cfg)
         assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, pl.blk_m)
     # FP8 follows the same rule (t >= 8 p of its 128x128x128 tile -> 256x256x128)

@@ -1,7 +1,7 @@
 """Parity where the kernels run at full size, through the C ABI.
 
-* Interior 256x256 tiles (the tile every problem with t >= 8p uses): integer
-  inputs, every operand contiguity, data-parallel and Stream-K (both fixups),
+* Interior 256x256 tiles (the tile of every FP16/BF16 problem with t >= 2p, FP8
+  t >= 8p): integer inputs, every operand contiguity, data-parallel and Stream-K (both fixups),
   row- and column-major C -- bit-exact against the oracle.
 * The precision set (BF16 and FP8 e4m3 with per-tensor absmax scales, N(0,1)
   from seed 2, BF16 output) on 8192^3, 256x256x65536 and 4096x1024x4096 in
