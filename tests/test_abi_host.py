@@ -241,12 +241,22 @@ def test_grouped_plan_matches_schedule_oracle(shapes, p, sched, grid):
 
 
 def test_auto_tile_and_schedule_policy():
-    # FP16/BF16 without a tile: 128x128 unless 2 full waves of it (t >= 2 p)
+    # FP16/BF16 without a tile: 128x128 unless 2 full waves of it (t >= 2 p);
+    # small problems take 64x64 (fewer than 64 such tiles: Stream-K; at most
+    # CUs 128x128 tiles and k <= 4096: data-parallel)
     cfg = S.make_config(wg_slots=512)
-    for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 256), (4096, 4096, 256), (4096, 2048, 128),
-                          (4096, 4096 - 128, 128), (4096 + 128, 4096, 256), (256, 256, 128)):
-        st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="bf16", c_type="f32"), cfg)
-        assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, pl.blk_m)
+    # (the schedules of the 256x256 cases are not checked: wg_slots = 512 is
+    # the 128x128 kernel's slot count, not the 256x256 one's)
+    for (m, n, k, blk_m, sched) in ((8192, 8192, 512, 256, None), (8192, 4096, 512, 256, None),
+                                    (4096, 4096, 512, 256, None), (4096, 2048, 512, 128, S.SK_SCHED_DP),
+                                    (4096, 4096 - 128, 512, 128, S.SK_SCHED_DP),
+                                    (4096 + 128, 4096, 512, 256, None),
+                                    (256, 256, 512, 64, None), (512, 448, 2048, 64, S.SK_SCHED_SK),
+                                    (2048, 2048, 4096, 64, S.SK_SCHED_DP), (2048, 2048, 4104, 128, S.SK_SCHED_SK),
+                                    (2048, 2048 + 128, 2048, 128, S.SK_SCHED_DP)):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type="bf16", c_type="f32"), cfg)
+        assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, k, pl.blk_m)
+        assert sched is None or pl.sched == sched, (m, n, k, pl.sched)
     # FP8 follows the same rule (t >= 8 p of its 128x128x128 tile -> 256x256x128)
     for (m, n, blk_m) in ((8192, 8192, 256), (8192, 4096, 128), (256, 256, 128)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=512, ab_type="f8e4m3", c_type="bf16", a_scale=0.5, b_scale=0.5), cfg)
@@ -282,7 +292,8 @@ def test_owner_peer_gate():
         d = desc(m=m, n=n, k=k, ab_type=dt, c_type="f64" if dt == "f64" else "f32")
         for fx in ("auto", "serial", "spread"):
             for sched in ("auto", "sk"):
-                st, pl = S.sk_plan(d, S.make_config(sched=sched, wg_slots=256, fixup=fx))
+                blk = (128, 128, 64) if dt == "bf16" else None     # one tile (the default would be 64x64)
+                st, pl = S.sk_plan(d, S.make_config(sched=sched, wg_slots=256, fixup=fx, blk=blk))
                 assert st == S.SK_OK, (m, n, k, dt, fx, sched)
                 assert pl.tiles == 1 and pl.max_peers <= S.SK_MAX_PEERS and pl.grid == pl.max_peers + 1, \
                     (pl.grid, pl.max_peers)

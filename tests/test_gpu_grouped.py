@@ -76,6 +76,22 @@ def test_grouped_integer_exact_and_trace(sched, grid, slots):
     compare_trace(R.read_trace(tr), plan, [(p["m"], p["n"], p["k"]) for p in probs])
 
 
+@pytest.mark.parametrize("sched", ["sk", "dp"])
+def test_grouped_64_tile_integer_exact_and_trace(sched):
+    # the 64x64 tile the automatic policy gives small batches
+    say(f"grouped 64x64 sched={sched}")
+    probs = make_batch(SHAPES, "f16", "f32", "int4", 60)
+    tr = torch.zeros(8 + 8 * 16384, dtype=torch.int32, device="cuda")
+    cfg = S.make_config(sched=sched, blk=(64, 64, 64), grid=0 if sched == "dp" else 97,
+                        trace_ptr=tr.data_ptr(), trace_capacity=16384)
+    ws = R.Workspace("cuda")
+    plan, raw = R.gemm_grouped([p["d"] for p in probs], cfg=cfg, ws=ws)
+    torch.cuda.synchronize()
+    ws.check()
+    check_results(probs, "f16", "f32", "int4")
+    compare_trace(R.read_trace(tr), plan, [(p["m"], p["n"], p["k"]) for p in probs])
+
+
 @pytest.mark.parametrize("ab,ct", [("f64", "f64"), ("f16", "f16"), ("bf16", "bf16"), ("f8e4m3", "f32")])
 def test_grouped_dtypes_real_valued(ab, ct):
     shapes = [(m, n, (k + 127) // 128 * 128) for (m, n, k) in SHAPES[:12]]
