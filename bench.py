@@ -311,11 +311,35 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def gpu_error_vs(cref, m, n, k, A, B, ct):
+    """||C - Cref||_F / (||A||_F ||B||_F) of the library's result on the
+    stored inputs A, B against an oracle result Cref (and, for a 16-bit
+    output, the same statistic of Cref's own rounding to that type, which
+    the error cannot go below)."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2301_03598_amd import runtime as R
+    Ad, Bd = A.to("cuda"), B.to("cuda")
+    C = torch.empty((m, n), dtype=W.torch_dtype(ct), device="cuda")
+    R.gemm(m, n, k, Ad, Bd, C, c_type=ct)
+    torch.cuda.synchronize()
+    got = C.cpu().double().numpy()
+    den = float(np.linalg.norm(oracle.decode_operand(A)) * np.linalg.norm(oracle.decode_operand(B)))
+    out = {"err": float(np.linalg.norm(got - cref) / den)}
+    if ct in ("bf16", "f16"):
+        out["output_rounding"] = float(np.linalg.norm(oracle.decode(oracle.round_to(cref, ct), ct) - cref) / den)
+    return {k2: float(f"{v:.4g}") for k2, v in out.items()}
+
+
 def cpu_baseline(budget_flops=7.0e11):
     """The CPU oracle, as it stands, on a bounded sample of the sweep (the
     problems in draw order whose flops fit the budget, FP16 inputs), plus
     configuration 1 (FP64 384x384x1024) and the precision set's
-    4096x1024x4096 on BF16 inputs, each timed once."""
+    4096x1024x4096 on BF16 and FP8 inputs, each timed once; for these three
+    the library's error against the oracle result is reported beside the
+    timing."""
     import oracle
     import workloads as W
     shapes = W.sweep_shapes()
@@ -336,12 +360,17 @@ def cpu_baseline(budget_flops=7.0e11):
     for name, (m, n, k), ab, ct, dist, seed in (("config1_f64_384x384x1024", (384, 384, 1024), "f64", "f64",
                                                   "uniform", 0),
                                                  ("precision_c_bf16_4096x1024x4096", (4096, 1024, 4096), "bf16",
+                                                  "bf16", "normal", 2),
+                                                 ("precision_c_f8e4m3_4096x1024x4096", (4096, 1024, 4096), "f8e4m3",
                                                   "bf16", "normal", 2)):
         A, B = W.gemm_operands(m, n, k, ab, seed, dist)
         t0 = time.perf_counter()
-        oracle.gemm(m, n, k, A, B, c_type=ct)
+        cref = oracle.gemm(m, n, k, A, B, c_type=ct)
         dt = time.perf_counter() - t0
         extra[name] = {"gflops": round(2.0 * m * n * k / dt / 1e9, 2), "s": round(dt, 3)}
+        # the same inputs through the library (default configuration): its
+        # normwise error against this oracle result
+        extra[name]["gpu_rel_err"] = gpu_error_vs(cref, m, n, k, A, B, ct)
     cores = int(os.environ.get("OMP_NUM_THREADS", 0) or len(os.sched_getaffinity(0)))
     return {"value": round(tot / t / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "cpu": cpu_model(),
