@@ -131,8 +131,10 @@ typedef struct {
  *                   only: a call with any split tile then reports
  *                   SK_ERR_TIMEOUT and its results are undefined).
  *  fixup            SK_FIXUP_*: how split tiles are reconciled.
- *  model_bw         bytes per microsecond of the memory term of the grid
- *                   model (spread fixup); 0 = the library's constant.
+ *  model_bw         device bytes per microsecond for an optional memory term
+ *                   of the grid model: every workgroup of a plan that splits
+ *                   tiles is charged 2 BM BN acc_bytes / model_bw for writing
+ *                   and reading back its partial tile; 0 = no memory term.
  */
 typedef struct {
     int32_t sched;

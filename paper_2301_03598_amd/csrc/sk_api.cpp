@@ -55,6 +55,10 @@ const TileDef *tiles_for(int ab, int *n) {
 // partials whatever the peer count, so its d is small.
 struct Model {
     double a, b, c, d;
+    // optional memory term (off by default): microseconds per workgroup
+    // that writes and reads back one partial tile, charged to every
+    // workgroup of a plan that splits tiles -- 2 BM BN acc_bytes / bandwidth
+    double mem = 0.0;
 };
 
 Model default_model(int ab, int bm, bool spread) {
@@ -227,6 +231,17 @@ sk_status_t query_slots(const KernelKey &key, int *slots) {
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Appendix A.1's per-workgroup time of basic Stream-K on g workgroups,
+// a + b [peers > 1] + c ItersPerCta(g) + d (peers - 1), plus the optional
+// memory term mem * g [peers > 1] for the partial-tile traffic, which grows
+// with the number of workgroups that emit partials.
+double model_time(int64_t T, int64_t I, int64_t g, const Model &m) {
+    const int64_t ipc = cdiv(T, g);
+    const int64_t peers = cdiv(I, ipc);
+    const double split = peers > 1 ? 1.0 : 0.0;
+    return m.a + m.b * split + m.c * (double)ipc + m.d * (double)(peers - 1) + m.mem * (double)g * split;
+}
+
 // Appendix A.1: g* = argmin over g in [1, min(p, T)] of
 //   a + b [peers > 1] + c ItersPerCta(g) + d (peers - 1),
 // ItersPerCta(g) = ceil(T / g), peers = ceil(I / ItersPerCta(g)); ties take
@@ -238,10 +253,7 @@ int model_grid(int64_t T, int64_t I, int p, const Model &m, Ok ok) {
     std::vector<std::pair<double, int>> cand;
     cand.reserve((size_t)gmax);
     for (int64_t g = 1; g <= gmax; ++g) {
-        const int64_t ipc = cdiv(T, g);
-        const int64_t peers = cdiv(I, ipc);
-        const double v = m.a + m.b * (peers > 1 ? 1.0 : 0.0) + m.c * (double)ipc + m.d * (double)(peers - 1);
-        cand.push_back({v, (int)g});
+        cand.push_back({model_time(T, I, g, m), (int)g});
     }
     size_t best = 0;
     for (size_t i = 1; i < cand.size(); ++i)
@@ -400,11 +412,6 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
     return SK_OK;
 }
 
-double model_time(int64_t T, int64_t I, int64_t g, const Model &m) {
-    const int64_t ipc = cdiv(T, g);
-    const int64_t peers = cdiv(I, ipc);
-    return m.a + m.b * (peers > 1 ? 1.0 : 0.0) + m.c * (double)ipc + m.d * (double)(peers - 1);
-}
 
 // Owners with at least this many peers make the automatic fixup the spread
 // one (with a single peer the serial fixup moves fewer bytes for the same
@@ -441,6 +448,10 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     Model m_spread = default_model(c.key.ab_type, c.tile.bm, true);
     if (cfg && (cfg->model_a != 0.0 || cfg->model_b != 0.0 || cfg->model_c != 0.0 || cfg->model_d != 0.0))
         m_serial = m_spread = Model{cfg->model_a, cfg->model_b, cfg->model_c, cfg->model_d};
+    if (cfg && cfg->model_bw > 0.0) {
+        const double acc = c.key.ab_type == SK_F64 ? 8.0 : 4.0;
+        m_serial.mem = m_spread.mem = 2.0 * (double)c.tile.bm * (double)c.tile.bn * acc / cfg->model_bw;
+    }
     const int64_t t = c.tiles;
     pl->xcd_remap = (cfg && (cfg->flags & SK_FLAG_NO_XCD_REMAP)) ? 0 : 1;
     if (t == 0) {

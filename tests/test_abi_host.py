@@ -344,3 +344,19 @@ def test_workspace_reserves_flag_region_for_every_schedule():
         assert st == S.SK_OK and pl.workspace_bytes >= base + per * 100 * slot
     assert S.sk_plan(d, S.make_config(sched="sk", grid=S.SK_MAX_GRID + 1, wg_slots=4096))[0] == \
         S.SK_ERR_INVALID_VALUE
+
+
+def test_model_memory_term():
+    # the optional memory term charges every workgroup of a tile-splitting
+    # plan for writing and reading back a partial tile: a scarce bandwidth
+    # pushes the model's grid down, an ample one leaves it unchanged
+    d = desc(m=256, n=256, k=65536, ab_type="bf16", c_type="f32")
+    grids = {}
+    for bw in (0.0, 1e12, 4e6, 1e4):
+        cfg = S.make_config(sched="sk", blk=(128, 128, 64), wg_slots=512, fixup="spread")
+        cfg.model_bw = bw
+        st, pl = S.sk_plan(d, cfg)
+        assert st == S.SK_OK
+        grids[bw] = pl.grid
+    assert grids[1e12] == grids[0.0]
+    assert grids[1e4] < grids[4e6] <= grids[0.0]
