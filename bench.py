@@ -430,10 +430,11 @@ def extended():
     return out
 
 
-def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20) -> dict:
+def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0) -> dict:
     """One precision-set style GEMM (N(0,1) operands from seed 2, BF16 output
-    for 16-bit and FP8 inputs, FP64 for FP64), default configuration: 3
-    warm-up launches, then `reps` timed back to back."""
+    for 16-bit and FP8 inputs, FP64 for FP64), default configuration (plus
+    the given SK_FLAG_* bits): 3 warm-up launches, then `reps` timed back to
+    back."""
     import torch
     import workloads as W
     from paper_2301_03598_amd import runtime as R
@@ -446,7 +447,7 @@ def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20) -> dict:
     W.device_fill_(A, "normal", gen)
     W.device_fill_(B, "normal", gen)
     C = torch.empty(m * n, dtype=W.torch_dtype(ct), device="cuda")
-    cfg = S.make_config()
+    cfg = S.make_config(flags=flags)
     d = S.make_desc(m, n, k, A, B, C, ab_type=ab, c_type=ct, a_scale=1.0, b_scale=1.0)
     st, pl = S.sk_plan(d, cfg)
     S.check(st, "sk_plan")
@@ -465,7 +466,7 @@ def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20) -> dict:
     return {"gemm": f"{m}x{n}x{k}", "ab": ab, "c": ct, "reps": reps, "ms": round(ms, 4),
             "tflops": round(tf, 1), "pct_peak": round(100 * tf / PEAK_TFLOPS[ab], 2),
             "sched": S.SCHED_NAME.get(pl.sched, pl.sched), "grid": pl.grid,
-            "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}"}
+            "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}", "flags": flags, "xcd_remap": pl.xcd_remap}
 
 
 def grouped_leg(tune: bool = True):
@@ -586,6 +587,8 @@ def main():
     ap.add_argument("--gemm", nargs=4, metavar=("M", "N", "K", "AB"),
                     help="time one GEMM of the given shape and input dtype (default configuration) "
                          "and print its JSON; for profiling a single kernel")
+    ap.add_argument("--gemm-flags", type=int, default=0,
+                    help="SK_FLAG_* bits for --gemm (1: no XCD remap, 2: row-major tile order)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -595,7 +598,7 @@ def main():
         S.lib()
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         m, n, k = (int(v) for v in args.gemm[:3])
-        print(json.dumps(one_gemm(m, n, k, args.gemm[3])), flush=True)
+        print(json.dumps(one_gemm(m, n, k, args.gemm[3], flags=args.gemm_flags)), flush=True)
         return
     if args.copy_calibration:
         import torch
