@@ -150,10 +150,13 @@ constexpr int64_t kBigTileWaves16 = 2;      // FP16 / BF16
 // take the 64x64 tile (measured per problem over the FP16 sweep, every
 // problem under every configuration: the sum of per-GEMM times falls from
 // 82.6 to 75.1 ms, geometric-mean speedup 1.25): basic Stream-K while it
-// has fewer than kTinySkTiles tiles, else data-parallel for problems of at
-// most CUs 128x128 tiles and k <= kTinyDpMaxK (deeper ones keep the
-// 128x128 tile's Stream-K split, which wins there).
+// has fewer than kTinySkTiles tiles and k <= kTinySkMaxK, else
+// data-parallel for problems of at most 3/4 CUs 128x128 tiles and k <=
+// kTinyDpMaxK.  Deeper or larger ones keep the 128x128 tile, whose
+// Stream-K split wins there (256x256x65536: 30 vs 35 us on the 64x64
+// tile; 4096x1024x4096, 256 tiles: 46 vs 76 us).
 constexpr int64_t kTinySkTiles = 64;
+constexpr int64_t kTinySkMaxK = 8192;
 constexpr int64_t kTinyDpMaxK = 4096;
 
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
@@ -391,7 +394,8 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
                 s = query_cus(&cus);
                 if (s != SK_OK) return s;
             }
-            if (t_tiny < kTinySkTiles || (t_small <= cus && kmax <= kTinyDpMaxK)) c->tile = tiny;
+            if ((t_tiny < kTinySkTiles && kmax <= kTinySkMaxK) || (4 * t_small <= 3 * (int64_t)cus && kmax <= kTinyDpMaxK))
+                c->tile = tiny;
         }
     }
     c->key = KernelKey{d[0].ab_type, c->tile.bm, c->tile.bn, a_kcontig(d[0]), b_kcontig(d[0]), grouped, false};

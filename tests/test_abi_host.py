@@ -242,8 +242,8 @@ def test_grouped_plan_matches_schedule_oracle(shapes, p, sched, grid):
 
 def test_auto_tile_and_schedule_policy():
     # FP16/BF16 without a tile: 128x128 unless 2 full waves of it (t >= 2 p);
-    # small problems take 64x64 (fewer than 64 such tiles: Stream-K; at most
-    # CUs 128x128 tiles and k <= 4096: data-parallel)
+    # small problems take 64x64 (fewer than 64 such tiles and k <= 8192:
+    # Stream-K; at most 3/4 CUs 128x128 tiles and k <= 4096: data-parallel)
     cfg = S.make_config(wg_slots=512)
     # (the schedules of the 256x256 cases are not checked: wg_slots = 512 is
     # the 128x128 kernel's slot count, not the 256x256 one's)
@@ -252,7 +252,10 @@ def test_auto_tile_and_schedule_policy():
                                     (4096, 4096 - 128, 512, 128, S.SK_SCHED_DP),
                                     (4096 + 128, 4096, 512, 256, None),
                                     (256, 256, 512, 64, None), (512, 448, 2048, 64, S.SK_SCHED_SK),
-                                    (2048, 2048, 4096, 64, S.SK_SCHED_DP), (2048, 2048, 4104, 128, S.SK_SCHED_SK),
+                                    (256, 256, 65536, 128, S.SK_SCHED_SK),
+                                    (2048, 1536, 4096, 64, S.SK_SCHED_DP), (2048, 1536, 4104, 128, S.SK_SCHED_SK),
+                                    (2048, 1536 + 128, 2048, 128, S.SK_SCHED_SK),
+                                    (4096, 1024, 4096, 128, S.SK_SCHED_SK),
                                     (2048, 2048 + 128, 2048, 128, S.SK_SCHED_DP)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type="bf16", c_type="f32"), cfg)
         assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, k, pl.blk_m)
