@@ -159,6 +159,42 @@ constexpr int64_t kTinySkTiles = 64;
 constexpr int64_t kTinySkMaxK = 8192;
 constexpr int64_t kTinyDpMaxK = 4096;
 
+// Schedule refinements of the FP16/BF16 default, measured per problem over
+// two FP16 geometry sweeps (2 x 2048 GEMMs, every problem under every
+// configuration; gains are of the summed per-GEMM time):
+//  * 64x64 tile, fewer than 1.5 CUs' worth of tiles, at least kDeepIters
+//    k-iterations per tile: basic Stream-K instead of one workgroup per tile
+//    (these problems' own time -12 %, -23 % below one CU's worth; sweep
+//    +1.1 %; from 1.5 CUs' worth on, one workgroup per tile is faster);
+//  * 128x128 tile under Stream-K: a k-aligned split (below, sweep +1.7 %);
+//  * 256x256 tile past a full wave with a last partial wave of at most
+//    kTailNum / kTailDen of the slots and at least kDeepIters k-iterations
+//    per tile: data-parallel waves + one-tile Stream-K (section 5.2) instead
+//    of a nearly empty last data-parallel wave (2792x6064x7048: 418 -> 295 us;
+//    sweep +0.8 %).  With a fuller last wave or shallower k the partial-tile
+//    traffic of the split costs more than the idle slots.
+constexpr int64_t kDeepIters = 32;
+constexpr int64_t kTailNum = 3, kTailDen = 10;
+
+// k-aligned Stream-K split: s workgroups per tile, each an equal k-range,
+// for the largest s <= SK_MAX_PEERS + 1 that divides the tile's iteration
+// count I with s t <= p; used when it keeps at least half of the slots busy
+// (2 s t >= p).  The paper's even split over the model's grid starts the
+// workgroups of neighbouring tiles at unrelated k offsets, so concurrently
+// running workgroups share no operand k-slices in their XCD's L2; with equal
+// k-ranges those of the same range index run the same k-slices together.
+// Measured (FP16, 128x128 tiles, t <= CUs, k >= 4096): the summed time of
+// the problems with 2 s t >= p falls by 9-27 % against the model's grid
+// (by more the closer s t comes to p); with fewer busy slots the model's
+// grid wins.  Single GEMMs only (a grouped call's tiles differ in I).
+int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p) {
+    int64_t best = 1;
+    const int64_t smax = std::min<int64_t>(iters_per_tile, SK_MAX_PEERS + 1);
+    for (int64_t s = 2; s <= smax; ++s)
+        if (iters_per_tile % s == 0 && s * tiles <= p) best = s;
+    return (best >= 2 && 2 * best * tiles >= p) ? best : 1;
+}
+
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
     int n = 0;
     const TileDef *t = tiles_for(ab, &n);
@@ -506,6 +542,7 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         return gs;
     };
     int fix = SK_FIXUP_SERIAL;
+    int64_t aligned_s = 1;     // > 1: the automatic schedule's k-aligned split
     if (sched == SK_SCHED_AUTO) {
         // Measured on MI355X: Stream-K pays off while the tiles give no CU
         // more than one workgroup (t <= CUs: a lone workgroup leaves its
@@ -521,17 +558,29 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         // above 43.7, DP 30.6 TFLOP/s): the paper's two-tile hybrid.
         // the 64x64 tile of the 16-bit and FP8 types: Stream-K only below
         // kTinySkTiles tiles, data-parallel otherwise (see the tile choice)
-        const int64_t sk_tiles = (c.tile.bm <= 64 && c.key.ab_type != SK_F64) ? kTinySkTiles - 1 : cus;
+        const bool half = c.key.ab_type == SK_F16 || c.key.ab_type == SK_BF16;
+        const bool single = c.probs.size() == 1;
+        int64_t sk_tiles = (c.tile.bm <= 64 && c.key.ab_type != SK_F64) ? kTinySkTiles - 1 : cus;
+        if (half && c.tile.bm <= 64 && c.imax >= kDeepIters) sk_tiles = std::max<int64_t>(sk_tiles, 3 * (int64_t)cus / 2 - 1);
         if (c.key.ab_type == SK_F64) sched = SK_SCHED_2TILE_SK_DP;
         else if (t <= sk_tiles) {
             sched = SK_SCHED_SK;
             // a model grid of exactly one workgroup per tile (one problem)
-            // is the data-parallel schedule: run the data-parallel kernel
+            // is the data-parallel schedule: run the data-parallel kernel;
+            // any other model grid of a 16-bit 128x128 problem gives way to
+            // a k-aligned split that fills half of the slots
             int f0 = 0;
-            if (user_grid == 0 && c.probs.size() == 1 && std::min<int64_t>(sk_model(&f0), c.iters) == t)
+            if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t)
                 sched = SK_SCHED_DP;
+            else if (half && single && user_grid == 0 && c.tile.bm == 128)
+                aligned_s = aligned_split(t, c.imax, pg);
         } else {
             sched = SK_SCHED_DP;
+            const int64_t tail = t % p;
+            if (half && single && user_grid == 0 && c.tile.bm >= 256 && t > p && tail > 0 &&
+                kTailDen * tail <= kTailNum * (int64_t)p && c.imax >= kDeepIters &&
+                c.max_peers(c.tile_iter_begin(t - tail), c.region_iters(t - tail, t), pg) <= SK_MAX_PEERS)
+                sched = SK_SCHED_DP_1TILE_SK;
         }
     }
     if (sched == SK_SCHED_DP) {
@@ -549,8 +598,8 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         sched = SK_SCHED_SK;
         skb = 0;
         ske = t;
-        model_g = user_grid == 0;
-        g = model_g ? sk_model(&fix) : user_grid;
+        model_g = user_grid == 0 && aligned_s == 1;
+        g = model_g ? sk_model(&fix) : (aligned_s > 1 ? aligned_s * t : user_grid);
     } else if (r == 0) {
         // perfect quantisation: data-parallel waves only
         sched = SK_SCHED_DP_1TILE_SK;

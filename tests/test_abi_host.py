@@ -177,6 +177,15 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
     else:
         osched, ogrid = sched, grid
     op = O.plan_problems(probs, p=p, sched=osched, grid=ogrid, consts=MODEL, threshold=threshold or 2)
+    if sched == S.SK_SCHED_AUTO and grid == 0 and pl.sched == S.SK_SCHED_SK and pl.grid != op.g:
+        # the library's k-aligned split instead of the model's grid: s
+        # workgroups per tile, s dividing the tile's iteration count, filling
+        # at least half of the slots; the oracle plans that grid
+        s_, t_ = pl.grid // pl.tiles, pl.tiles
+        it = probs.total // t_
+        assert len(shapes) == 1 and pl.grid == s_ * t_ and s_ >= 2 and it % s_ == 0
+        assert s_ * t_ <= p <= 2 * s_ * t_ and s_ <= S.SK_MAX_PEERS + 1
+        op = O.plan_problems(probs, p=p, sched=osched, grid=pl.grid, consts=MODEL, threshold=threshold or 2)
     omp = oracle_max_peers(probs, op)
     if omp > S.SK_MAX_PEERS:
         # the paper's plan needs an owner with more peers than the library
@@ -286,6 +295,58 @@ def test_auto_tile_and_schedule_policy():
     # an explicit grid is honoured as Stream-K even when it equals t
     st, pl = S.sk_plan(d1, S.make_config(blk=blk, wg_slots=512, grid=64))
     assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK and pl.grid == 64
+
+
+def test_auto_refinements():
+    # FP16/BF16 only; measured rules, not the paper's
+    cfg = S.make_config(wg_slots=512)
+
+    def plan(m, n, k, dt="bf16", c=cfg):
+        st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type=dt, c_type="f32" if dt != "f8e4m3" else "bf16",
+                                a_scale=0.5 if dt == "f8e4m3" else 1.0, b_scale=0.5 if dt == "f8e4m3" else 1.0), c)
+        assert st == S.SK_OK, S.sk_status_string(st)
+        return pl
+    # 64x64 tile, fewer than 1.5 CUs' worth of tiles: Stream-K from 32
+    # k-iterations per tile on, one workgroup per tile below (1280 slots:
+    # five 64x64 workgroups per CU by LDS, 256 CUs)
+    c64 = S.make_config(wg_slots=1280)
+    pl = plan(1024, 1024, 2048, c=c64)
+    assert (pl.blk_m, pl.tiles, pl.sched) == (64, 256, S.SK_SCHED_SK) and pl.grid > 256
+    pl = plan(1024, 1024, 1024, c=c64)
+    assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_DP)
+    pl = plan(2048, 1536, 4096, c=c64)                 # 768 such tiles: data-parallel
+    assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_DP)
+    pl = plan(1280, 1280, 2048, c=c64)                 # 400 >= 384 such tiles: data-parallel
+    assert (pl.blk_m, pl.tiles, pl.sched) == (64, 400, S.SK_SCHED_DP)
+    # 128x128 Stream-K: k-aligned split, s | I, s t <= p <= 2 s t
+    for (m, n, k, g) in ((2048, 1664, 2048, 416), (4096, 1024, 4096, 512), (1024, 1024, 8192, 512),
+                         (128 * 9, 128 * 20, 8192, 360)):
+        pl = plan(m, n, k)
+        assert (pl.blk_m, pl.sched, pl.grid) == (128, S.SK_SCHED_SK, g), (m, n, k, pl.grid)
+        assert pl.max_peers == g // pl.tiles - 1
+    # no divisor of I = 127 fills half the slots: the model's grid
+    pl = plan(1024, 1024, 127 * 64)
+    assert pl.sched == S.SK_SCHED_SK and pl.grid % pl.tiles != 0
+    # FP8 and grouped calls keep the model's grid
+    pl = plan(1024, 1024, 127 * 64 + 64, dt="f8e4m3")
+    assert pl.blk_m == 128 and pl.grid != 2 * pl.tiles or pl.sched != S.SK_SCHED_SK
+    d = desc(m=1024, n=1024, k=8192, ab_type="bf16", c_type="f32")
+    st, pl = S.sk_plan([d, d], S.make_config(blk=(128, 128, 64), wg_slots=512))
+    assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK
+    # 256x256 past a full wave: DP waves + one-tile Stream-K when the last
+    # wave holds at most 3/10 of the slots and k has >= 32 iterations per tile
+    c256 = S.make_config(wg_slots=256)                 # one 256x256 workgroup per CU
+    pl = plan(4096, 4096 + 256, 4096, c=c256)          # 272 tiles: 256 + 16
+    assert (pl.blk_m, pl.sched, pl.grid, pl.dp_tiles) == (256, S.SK_SCHED_DP_1TILE_SK, 256, 256)
+    assert pl.max_peers <= S.SK_MAX_PEERS
+    pl = plan(256 * 257, 256, 4096, c=c256)            # one leftover tile of 64 iterations: 63 peers
+    assert (pl.sched, pl.max_peers) == (S.SK_SCHED_DP_1TILE_SK, 63)
+    for (m, n, k) in ((4096, 4096 + 256, 1024),          # 16 iterations per tile
+                      (4096, 256 * 22, 4096),            # last wave 96 > 76.8 slots
+                      (4096, 4096, 4096),                # no partial wave
+                      (256 * 257, 256, 8192)):           # one leftover tile: 127 peers
+        pl = plan(m, n, k, c=c256)
+        assert (pl.blk_m, pl.sched) == (256, S.SK_SCHED_DP), (m, n, k, pl.sched)
 
 
 def test_owner_peer_gate():

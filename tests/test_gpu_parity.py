@@ -57,7 +57,7 @@ def check_case(m, n, k, ab, ct, *, dist, seed=0, a_order="row", b_order="row", c
         Cop = W.store(C0, ct, c_order)
         C0 = oracle.decode_operand(Cop)          # the exact stored C values
     Ct, plan, tr = run_gemm(m, n, k, dev(A), dev(B), c_type=ct, c_order=c_order, C0=C0, alpha=alpha,
-                            beta=beta, cfg=cfg, ws=ws, trace_cap=4096 if trace else 0)
+                            beta=beta, cfg=cfg, ws=ws, trace_cap=16384 if trace else 0)
     cref = oracle.gemm(m, n, k, A, B, Cop, alpha=alpha, beta=beta, c_type=ct)
     if dist == "int4":
         got = c_bits(Ct, m, n, c_order)
@@ -156,6 +156,21 @@ def test_hybrids_on_few_slots(sched, slots, ws):
     check_case(m, n, k, "f64", "f64", dist="int4", cfg=cfg, ws=ws)
     cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots)
     check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
+
+
+@pytest.mark.parametrize("m,n,k,blk_m,sched", [
+    (1024, 1024, 2048, 64, S.SK_SCHED_SK),              # 256 64x64 tiles, 32 iterations each
+    (2048, 1664, 2048, 128, S.SK_SCHED_SK),             # k-aligned split: 2 workgroups per tile
+    (4096, 4352, 2048, 256, S.SK_SCHED_DP_1TILE_SK)])   # 272 256x256 tiles: 256 DP + 16 split
+def test_default_schedule_refinements(m, n, k, blk_m, sched, ws):
+    # the default configuration's measured refinements of the 16-bit
+    # schedule, on the machine's own slot counts
+    _, plan = check_case(m, n, k, "bf16", "f32", dist="int4", ws=ws)
+    assert (plan.blk_m, plan.sched) == (blk_m, sched), (plan.blk_m, plan.sched, plan.grid)
+    if blk_m == 128:
+        assert plan.grid == 2 * plan.tiles and plan.max_peers == 1
+    if blk_m == 256:
+        assert plan.dp_tiles == plan.grid and plan.sk_tile_end - plan.sk_tile_begin == plan.tiles - plan.grid
 
 
 @pytest.mark.parametrize("m,n,k", [(384, 384, 64), (256, 640, 128)])
