@@ -175,6 +175,15 @@ constexpr int64_t kTinyDpMaxK = 4096;
 //    traffic of the split costs more than the idle slots.
 constexpr int64_t kDeepIters = 32;
 constexpr int64_t kTailNum = 3, kTailDen = 10;
+// A single GEMM with between kMidBigDp/kMidBigDen of the CUs and all CUs in
+// 256x256 tiles and at least kDeepIters k-iterations per tile takes that
+// tile, data-parallel (the 128x128 tile would give 2-4 partial waves of one
+// or two workgroups per CU; these problems' own time -11 %); from
+// kMidBigLo/kMidBigDen of the CUs on and with at least kMidBigSkIters
+// k-iterations per tile, basic Stream-K over the model's grid (-9 %;
+// shallower ones lose to the 128x128 tile).
+constexpr int64_t kMidBigLo = 4, kMidBigDp = 5, kMidBigDen = 8;
+constexpr int64_t kMidBigSkIters = 48;
 
 // k-aligned Stream-K split: s workgroups per tile, each an equal k-range,
 // for the largest s <= SK_MAX_PEERS + 1 that divides the tile's iteration
@@ -415,6 +424,23 @@ sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t
         }
         const int64_t waves = d[0].ab_type == SK_F8_E4M3 ? kBigTileWaves : kBigTileWaves16;
         if (t_small < waves * (int64_t)p_small) c->tile = small;
+        if (d[0].ab_type != SK_F8_E4M3 && c->tile.bm == small.bm && count == 1) {
+            // a deep GEMM with between half and all of a CU's worth of
+            // 256x256 tiles keeps the eight-wave tile (see kMidBig*)
+            const TileDef big = tiles_for(d[0].ab_type, &n)[0];
+            const Problem pb = to_problem(d[0], big.bm, big.bn, big.bk);
+            const int64_t t_big = cdiv(pb.m, big.bm) * (int64_t)pb.tiles_n;
+            int cus = 0;
+            if (cfg && cfg->wg_slots > 0) {
+                cus = std::max(1, cfg->wg_slots / lds_wgs_per_cu(small));
+            } else {
+                s = query_cus(&cus);
+                if (s != SK_OK) return s;
+            }
+            if (t_big <= cus && ((pb.iters >= kDeepIters && kMidBigDen * t_big >= kMidBigDp * (int64_t)cus) ||
+                                 (pb.iters >= kMidBigSkIters && kMidBigDen * t_big >= kMidBigLo * (int64_t)cus)))
+                c->tile = big;
+        }
         if (d[0].ab_type != SK_F8_E4M3 && c->tile.bm == small.bm) {
             const TileDef tiny = tiles_for(d[0].ab_type, &n)[2];
             int64_t t_tiny = 0, kmax = 0;
@@ -563,6 +589,9 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         int64_t sk_tiles = (c.tile.bm <= 64 && c.key.ab_type != SK_F64) ? kTinySkTiles - 1 : cus;
         if (half && c.tile.bm <= 64 && c.imax >= kDeepIters) sk_tiles = std::max<int64_t>(sk_tiles, 3 * (int64_t)cus / 2 - 1);
         if (c.key.ab_type == SK_F64) sched = SK_SCHED_2TILE_SK_DP;
+        else if (half && single && user_grid == 0 && c.tile.bm >= 256 && t <= cus &&
+                 kMidBigDen * t >= kMidBigDp * (int64_t)cus)
+            sched = SK_SCHED_DP;
         else if (t <= sk_tiles) {
             sched = SK_SCHED_SK;
             // a model grid of exactly one workgroup per tile (one problem)

@@ -333,6 +333,21 @@ def test_auto_refinements():
     d = desc(m=1024, n=1024, k=8192, ab_type="bf16", c_type="f32")
     st, pl = S.sk_plan([d, d], S.make_config(blk=(128, 128, 64), wg_slots=512))
     assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK
+    # deep single GEMMs with between half and all of the CUs' worth of
+    # 256x256 tiles keep that tile (here 256 CUs: two 128x128 workgroups per
+    # CU in 512 slots); shallow ones and grouped calls keep 128x128
+    for (m, n, k, blk_m) in ((4096, 2560, 4096, 256), (2048, 4096, 3072, 256), (4096, 4096, 2048, 256),
+                             (4096, 2560, 2048, 256), (2048, 4096, 2048, 128),
+                             (2048, 3840, 4096, 128), (4096, 2560, 1024, 128), (2048, 2048, 4096, 128)):
+        assert plan(m, n, k).blk_m == blk_m, (m, n, k)
+    d = desc(m=4096, n=2560, k=4096, ab_type="bf16", c_type="f32")
+    st, pl = S.sk_plan([d, d], cfg)
+    assert st == S.SK_OK and pl.blk_m == 256      # 320 tiles of 128x128 per problem: 2 p in all
+    st, pl = S.sk_plan([d], cfg)                  # one problem given as a list
+    assert st == S.SK_OK and pl.blk_m == 256
+    d = desc(m=2048, n=2560, k=4096, ab_type="bf16", c_type="f32")
+    st, pl = S.sk_plan([d, d], cfg)               # 2 x 80 256x256 tiles: not a single GEMM
+    assert st == S.SK_OK and pl.blk_m == 128
     # 256x256 past a full wave: DP waves + one-tile Stream-K when the last
     # wave holds at most 3/10 of the slots and k has >= 32 iterations per tile
     c256 = S.make_config(wg_slots=256)                 # one 256x256 workgroup per CU

@@ -161,7 +161,9 @@ def test_hybrids_on_few_slots(sched, slots, ws):
 @pytest.mark.parametrize("m,n,k,blk_m,sched", [
     (1024, 1024, 2048, 64, S.SK_SCHED_SK),              # 256 64x64 tiles, 32 iterations each
     (2048, 1664, 2048, 128, S.SK_SCHED_SK),             # k-aligned split: 2 workgroups per tile
-    (4096, 4352, 2048, 256, S.SK_SCHED_DP_1TILE_SK)])   # 272 256x256 tiles: 256 DP + 16 split
+    (4096, 4352, 2048, 256, S.SK_SCHED_DP_1TILE_SK),    # 272 256x256 tiles: 256 DP + 16 split
+    (4096, 2560, 2048, 256, S.SK_SCHED_DP),             # 160 256x256 tiles, one wave
+    (2048, 4096, 3072, 256, S.SK_SCHED_SK)])            # 128 256x256 tiles: Stream-K
 def test_default_schedule_refinements(m, n, k, blk_m, sched, ws):
     # the default configuration's measured refinements of the 16-bit
     # schedule, on the machine's own slot counts
@@ -169,7 +171,7 @@ def test_default_schedule_refinements(m, n, k, blk_m, sched, ws):
     assert (plan.blk_m, plan.sched) == (blk_m, sched), (plan.blk_m, plan.sched, plan.grid)
     if blk_m == 128:
         assert plan.grid == 2 * plan.tiles and plan.max_peers == 1
-    if blk_m == 256:
+    if sched == S.SK_SCHED_DP_1TILE_SK:
         assert plan.dp_tiles == plan.grid and plan.sk_tile_end - plan.sk_tile_begin == plan.tiles - plan.grid
 
 
