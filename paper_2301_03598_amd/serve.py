@@ -9,10 +9,13 @@ Requests (m, n, k, dtype) arrive over time.  The host loop
      launches run is admitted and overlaps with them on the device,
   4. polls completion events and records each request's latency.
 
-Concurrent persistent launches share the machine: each launch is planned on
-its share of the resident workgroup slots (slots / streams), so every
-workgroup of every launch in flight is co-resident and the Stream-K fixup
-waits always make progress.
+Concurrent persistent launches share the machine: each launch takes the tile
+the library picks for its batch on the whole machine and is planned on
+1 / streams of the resident slots of that tile's kernel, so every workgroup
+of every launch in flight is co-resident and the Stream-K fixup waits always
+make progress.  A wait that gives up anyway (its bound is real time) is
+reported when the loop ends: the run raises SkError(SK_ERR_TIMEOUT) instead
+of returning results that a fixup did not complete.
 
 Operands come from per-dtype device pools filled once (no host-to-device
 copies in the serving path); each request reads its own window of the pool
@@ -118,16 +121,26 @@ class Server:
         self.max_batch = max_batch
         self.max_batch_flops = max_batch_flops
         self.cfg_for = cfg_for
-        self.slots = None
+        self.slots: Dict[tuple, int] = {}
 
     # -- helpers -----------------------------------------------------------
-    def _slots_share(self, dtype: str) -> int:
-        if self.slots is None:
-            d = S.make_desc(256, 256, 256, 16, 16, 16, ab_type=dtype, c_type=C_TYPE[dtype])
-            st, pl = S.sk_plan(d, S.make_config(sched="sk"))
+    def _share(self, dtype: str, descs, cfg: S.sk_config_t) -> S.sk_config_t:
+        """cfg with the batch's tile fixed (the library's choice on the whole
+        machine unless cfg names one) and wg_slots set to this launch's share
+        of that tile's kernel's resident slots."""
+        if not (cfg.blk_m or cfg.blk_n or cfg.blk_k):
+            st, pl = S.sk_plan(descs, cfg)
             S.check(st, "sk_plan")
-            self.slots = pl.wg_slots
-        return max(1, self.slots // len(self.streams))
+            cfg.blk_m, cfg.blk_n, cfg.blk_k = pl.blk_m, pl.blk_n, pl.blk_k
+        key = (dtype, cfg.blk_m, cfg.blk_n, cfg.blk_k)
+        if key not in self.slots:
+            # (a one-workgroup Stream-K plan reports the kernel's slots)
+            st, pl = S.sk_plan(descs, S.make_config(sched="sk", blk=(cfg.blk_m, cfg.blk_n, cfg.blk_k), grid=1))
+            S.check(st, "sk_plan")
+            self.slots[key] = pl.wg_slots
+        cfg.wg_slots = max(1, self.slots[key] // len(self.streams))
+        cfg.grid = min(cfg.grid, cfg.wg_slots)
+        return cfg
 
     def _desc(self, r: Served) -> S.sk_gemm_desc_t:
         pool = self.pools[r.dtype]
@@ -152,6 +165,7 @@ class Server:
         max_q = 0
         qsamples = []
         done: List[Served] = []
+        used_streams = set()
         t0 = time.perf_counter()
         next_sample = 0.0
         while pending or queue or any(admitted.values()) or any(x is not None for x in inflight):
@@ -205,10 +219,10 @@ class Server:
                     fl += r.flops
                 descs = [self._desc(r) for r in batch]
                 cfg = self.cfg_for(dt, batch) if self.cfg_for else S.make_config()
-                cfg.wg_slots = self._slots_share(dt)
-                cfg.grid = min(cfg.grid, cfg.wg_slots)
+                cfg = self._share(dt, descs, cfg)
                 stream = self.streams[si]
                 plan, keep = R.gemm_grouped(descs, cfg=cfg, ws=self.ws[si], stream=stream)
+                used_streams.add(si)
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 tl = (time.perf_counter() - t0) / time_scale
@@ -218,6 +232,9 @@ class Server:
                 inflight[si] = (ev, batch, keep)
                 launches += 1
         end = (time.perf_counter() - t0) / time_scale
+        # a fixup wait that gave up in any launch of a stream: raise
+        for si in sorted(used_streams):
+            self.ws[si].check(self.streams[si].cuda_stream)
         lat = sorted((r.done - r.arrival) * 1e3 for r in done)
 
         def pct(q):
