@@ -195,7 +195,9 @@ constexpr int64_t kMidBigSkIters = 48;
 // Measured (FP16, 128x128 tiles, t <= CUs, k >= 4096): the summed time of
 // the problems with 2 s t >= p falls by 9-27 % against the model's grid
 // (by more the closer s t comes to p); with fewer busy slots the model's
-// grid wins.  Single GEMMs only (a grouped call's tiles differ in I).
+// grid wins.  FP8 (128x128x128): 2048x1664x4096 594 -> 935 TFLOP/s,
+// 3072x1280x6144 761 -> 1263, 1152x2560x8192 657 -> 1123.  Single GEMMs
+// only (a grouped call's tiles differ in I).
 int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p) {
     int64_t best = 1;
     const int64_t smax = std::min<int64_t>(iters_per_tile, SK_MAX_PEERS + 1);
@@ -601,7 +603,7 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             int f0 = 0;
             if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t)
                 sched = SK_SCHED_DP;
-            else if (half && single && user_grid == 0 && c.tile.bm == 128)
+            else if ((half || c.key.ab_type == SK_F8_E4M3) && single && user_grid == 0 && c.tile.bm == 128)
                 aligned_s = aligned_split(t, c.imax, pg);
         } else {
             sched = SK_SCHED_DP;

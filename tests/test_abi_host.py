@@ -327,9 +327,10 @@ def test_auto_refinements():
     # no divisor of I = 127 fills half the slots: the model's grid
     pl = plan(1024, 1024, 127 * 64)
     assert pl.sched == S.SK_SCHED_SK and pl.grid % pl.tiles != 0
-    # FP8 and grouped calls keep the model's grid
-    pl = plan(1024, 1024, 127 * 64 + 64, dt="f8e4m3")
-    assert pl.blk_m == 128 and pl.grid != 2 * pl.tiles or pl.sched != S.SK_SCHED_SK
+    # FP8's 128x128x128 tile too
+    pl = plan(2048, 1664, 4096, dt="f8e4m3")
+    assert (pl.blk_m, pl.blk_k, pl.sched, pl.grid) == (128, 128, S.SK_SCHED_SK, 416)
+    # grouped calls keep the model's grid
     d = desc(m=1024, n=1024, k=8192, ab_type="bf16", c_type="f32")
     st, pl = S.sk_plan([d, d], S.make_config(blk=(128, 128, 64), wg_slots=512))
     assert st == S.SK_OK and pl.sched == S.SK_SCHED_SK

@@ -158,16 +158,17 @@ def test_hybrids_on_few_slots(sched, slots, ws):
     check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
 
 
-@pytest.mark.parametrize("m,n,k,blk_m,sched", [
-    (1024, 1024, 2048, 64, S.SK_SCHED_SK),              # 256 64x64 tiles, 32 iterations each
-    (2048, 1664, 2048, 128, S.SK_SCHED_SK),             # k-aligned split: 2 workgroups per tile
-    (4096, 4352, 2048, 256, S.SK_SCHED_DP_1TILE_SK),    # 272 256x256 tiles: 256 DP + 16 split
-    (4096, 2560, 2048, 256, S.SK_SCHED_DP),             # 160 256x256 tiles, one wave
-    (2048, 4096, 3072, 256, S.SK_SCHED_SK)])            # 128 256x256 tiles: Stream-K
-def test_default_schedule_refinements(m, n, k, blk_m, sched, ws):
-    # the default configuration's measured refinements of the 16-bit
-    # schedule, on the machine's own slot counts
-    _, plan = check_case(m, n, k, "bf16", "f32", dist="int4", ws=ws)
+@pytest.mark.parametrize("ab,m,n,k,blk_m,sched", [
+    ("bf16", 1024, 1024, 2048, 64, S.SK_SCHED_SK),              # 256 64x64 tiles, 32 iterations each
+    ("bf16", 2048, 1664, 2048, 128, S.SK_SCHED_SK),             # k-aligned split: 2 workgroups per tile
+    ("f8e4m3", 2048, 1664, 4096, 128, S.SK_SCHED_SK),           # the same with FP8's 128x128x128 tile
+    ("bf16", 4096, 4352, 2048, 256, S.SK_SCHED_DP_1TILE_SK),    # 272 256x256 tiles: 256 DP + 16 split
+    ("bf16", 4096, 2560, 2048, 256, S.SK_SCHED_DP),             # 160 256x256 tiles, one wave
+    ("bf16", 2048, 4096, 3072, 256, S.SK_SCHED_SK)])            # 128 256x256 tiles: Stream-K
+def test_default_schedule_refinements(ab, m, n, k, blk_m, sched, ws):
+    # the default configuration's measured refinements of the schedule, on
+    # the machine's own slot counts
+    _, plan = check_case(m, n, k, ab, "f32", dist="int4", ws=ws)
     assert (plan.blk_m, plan.sched) == (blk_m, sched), (plan.blk_m, plan.sched, plan.grid)
     if blk_m == 128:
         assert plan.grid == 2 * plan.tiles and plan.max_peers == 1
