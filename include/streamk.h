@@ -120,6 +120,9 @@ typedef struct {
  *                   int32 {wg, seq, tile, k_begin, k_end, role, last_peer, x}
  *                   start at trace[8].  Records beyond trace_capacity are
  *                   dropped (the counter still counts them).
+ *                   Data-parallel tiles taken from the per-XCD queues (see
+ *                   SK_FLAG_STATIC_DP_TILES) are recorded under the
+ *                   workgroup that ran them, in its order.
  *                   role: 0 DP tile, 1 whole tile in one SK segment,
  *                   2 owner (its tile's later contributors end at last_peer),
  *                   3 producer (stores one partial tile), 4 slice reduction
@@ -153,6 +156,15 @@ typedef struct {
 
 #define SK_FLAG_NO_XCD_REMAP 0x1     /* keep logical workgroup id == hardware id */
 #define SK_FLAG_ROW_MAJOR_TILES 0x2  /* tile t -> (t / tiles_n, t % tiles_n) instead of banded order */
+/* A persistent launch with more data-parallel tiles than workgroups gives
+ * workgroup x the data-parallel tile x first, then takes the others from
+ * eight per-XCD queues (contiguous eighths of the remaining tiles, each in
+ * order, an emptied queue taking from the next XCDs' ones), so uneven
+ * tiles (grouped problems of different k) balance over the workgroups; the
+ * results are the same bits either way (no data-parallel tile is split).
+ * This flag keeps the static order of section 4's data-parallel schedule
+ * instead: tiles x, x + g, x + 2g, ... to workgroup x. */
+#define SK_FLAG_STATIC_DP_TILES 0x4
 
 /* Largest persistent grid, and the most peers one tile's owner may wait on
  * (plans beyond it are rejected with SK_ERR_UNSUPPORTED, or avoided when the

@@ -90,6 +90,7 @@ struct Params {
     int32_t xcd_remap;
     int32_t band;            // tile rasterisation band (1: row-major tiles)
     int32_t fixup;           // FIXUP_SERIAL or FIXUP_SPREAD
+    int32_t dyn_dp;          // 1: data-parallel tiles after the first from the per-XCD queues
     int64_t wait_ticks;      // bound of one fixup wait, in real-time-counter ticks (<= 0: give up at once)
     void *partials;          // partial-tile slots of BM*BN accumulators (see slot_first / slot_last)
     int32_t *flags;          // the fixed flag region, FLAG_STRIDE ints apart
@@ -111,8 +112,9 @@ constexpr int MAX_GRID = 1024;           // largest persistent grid
 constexpr int FLAG_REGION = 2 * MAX_GRID * FLAG_STRIDE * 4;
 // Header words.  A flag is raised by storing the call's epoch, derived from
 // HDR_GEN, so flags never need clearing; the last workgroup of a Stream-K
-// launch to finish (counted in HDR_DONE) advances HDR_GEN for the next call.
-constexpr int HDR_ERR = 0, HDR_GEN = 1, HDR_DONE = 2;
+// launch to finish (counted in HDR_DONE) advances HDR_GEN for the next call,
+// and returns the eight data-parallel tile queue counters HDR_NEXT + c to 0.
+constexpr int HDR_ERR = 0, HDR_GEN = 1, HDR_DONE = 2, HDR_NEXT = 3, XCDS = 8;
 // Owners wait on at most this many peers (one 64-lane polling round).
 constexpr int MAX_PEERS = 64;
 

@@ -1346,11 +1346,32 @@ __device__ __forceinline__ int tile_of_iter(const Params &p, int it) {
     }
 }
 
+// The next data-parallel tile of a persistent launch after its first wave
+// (tiles [0, g) go to workgroups 0..g-1): the tiles [g, dp_tiles) form eight
+// contiguous chunks, one per XCD, each taken in order through its own
+// counter, so the workgroups of one XCD keep neighbouring tiles (shared A
+// and B panels) in flight as a one-workgroup-per-tile launch does, while a
+// workgroup that drew short tiles simply takes more of them.  A workgroup
+// whose XCD's chunk is used up takes from the next XCDs' chunks.  Returns
+// an index into [0, dp_tiles - g), or dp_tiles - g when none is left.
+__device__ __forceinline__ int next_dp_tile(const Params &p, int xcd) {
+    const int D = p.dp_tiles - p.g;
+    for (int i = 0; i < XCDS; ++i) {
+        const int c = (xcd + i) % XCDS;
+        const int lo = (int)((int64_t)D * c / XCDS), hi = (int)((int64_t)D * (c + 1) / XCDS);
+        if (lo >= hi) continue;
+        const int v = __hip_atomic_fetch_add(p.hdr + HDR_NEXT + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v < hi - lo) return lo + v;
+    }
+    return D;
+}
+
 // ---------------------------------------------------------------------------
 // the kernel body
 // ---------------------------------------------------------------------------
 // One workgroup's work is a sequence of units: whole data-parallel tiles
-// (j = x, x+g, ...) and the segments of its Stream-K range, in the phase
+// (j = x, then x+g, x+2g, ... or the per-XCD queues' tiles) and the
+// segments of its Stream-K range, in the phase
 // order the plan asks for.  Keeping a single MAC-loop / fixup / epilogue site
 // keeps the code (and its register allocation) in one piece.
 //
@@ -1371,6 +1392,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     __shared__ __attribute__((aligned(16))) char lds1[C::STAGE];
     __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE >= 3 ? C::STAGE : 16];
     __shared__ __attribute__((aligned(16))) char lds3[C::NSTAGE >= 4 ? C::STAGE : 16];
+    __shared__ int next_dp;     // the next queued data-parallel tile, for all waves
     const LdsBufs bufs{lds0, lds1, lds2, lds3};
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
@@ -1407,6 +1429,11 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     int phase = 0;         // 0, 1: the two phases; 2: done
     int seq = 0;
     const bool dp_first = DP_ONLY || p.dp_first;
+    // data-parallel tiles after the first from the per-XCD queues: thread 0
+    // takes the next one as a tile starts (the atomic's latency hides under
+    // the MAC loop) and hands it to the workgroup after the epilogue
+    const bool dyn = !DP_ONLY && p.dyn_dp;
+    int queued = 0;
     while (true) {
         const bool dp_now = (phase == 0) == dp_first;
         int tile, k0, k1;
@@ -1415,7 +1442,11 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         if (dp_now) {
             if (j >= p.dp_tiles) { ++phase; continue; }
             tile = j < p.sk_tile_begin ? j : j - p.sk_tile_begin + p.sk_tile_end;
-            j += p.g;
+            if (dyn) {
+                if (tid0 == 0) queued = next_dp_tile(p, b % XCDS);
+            } else {
+                j += p.g;
+            }
         } else {
             if (DP_ONLY || it >= end) { ++phase; continue; }
             tile = tile_of_iter<C::GROUPED>(p, p.sk_iter_begin + it);
@@ -1474,6 +1505,12 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         store_tile<C>(P, tm, tn, acc, tid, (const char *)p.partials, x + 1, last, lds0, lds1);
         trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER), last, 0,
                   tid);
+        if (dp_now && dyn) {
+            if (tid0 == 0) next_dp = queued;
+            __syncthreads();
+            j = p.g + next_dp;
+            __syncthreads();
+        }
     }
     if constexpr (!DP_ONLY) {
         if (spread) {
@@ -1498,6 +1535,8 @@ __device__ __forceinline__ void sk_body(const Params &p) {
             const int done = __hip_atomic_fetch_add(p.hdr + HDR_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (done == p.g - 1) {
                 __hip_atomic_store(p.hdr + HDR_DONE, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int c = 0; c < XCDS; ++c)
+                    __hip_atomic_store(p.hdr + HDR_NEXT + c, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(p.hdr + HDR_GEN, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }

@@ -22,6 +22,7 @@ SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_SCHED_AUTO, SK_SCHED_DP, SK_SCHED_SK, SK_SCHED_DP_1TILE_SK, SK_SCHED_2TILE_SK_DP = range(5)
 SK_FLAG_NO_XCD_REMAP = 0x1
 SK_FLAG_ROW_MAJOR_TILES = 0x2
+SK_FLAG_STATIC_DP_TILES = 0x4
 SK_MAX_GRID, SK_MAX_PEERS = 1024, 64
 SK_FIXUP_AUTO, SK_FIXUP_SERIAL, SK_FIXUP_SPREAD = 0, 1, 2
 FIXUP = {"auto": SK_FIXUP_AUTO, "serial": SK_FIXUP_SERIAL, "spread": SK_FIXUP_SPREAD}

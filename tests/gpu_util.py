@@ -114,11 +114,16 @@ def oracle_segments(plan, shapes, c_order="row"):
 ROLE_REDUCE = 4
 
 
-def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4):
+def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4, static_dp=False):
     """The executed segments must be the schedule oracle's, record by record.
-    Slice reductions of the spread fixup (role 4) are checked separately:
-    every split tile's partial chunks are reduced exactly once, by each of its
-    contributors in turn, in ascending slices."""
+    A persistent launch with more data-parallel tiles than workgroups takes
+    them, after each workgroup's first, from per-XCD queues (unless
+    SK_FLAG_STATIC_DP_TILES, `static_dp`): then each workgroup's Stream-K
+    segments and first data-parallel tile are the oracle's, and the
+    data-parallel tiles, whichever workgroup ran them, are the oracle's, each
+    exactly once.  Slice reductions of the spread fixup (role 4) are checked
+    separately: every split tile's partial chunks are reduced exactly once, by
+    each of its contributors in turn, in ascending slices."""
     count, recs = trace
     segs = oracle_segments(plan, shapes, c_order)
     seg_recs = [r for r in recs if r[5] != ROLE_REDUCE]
@@ -128,10 +133,27 @@ def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4):
     got = {}
     for (wg, seq, tile, k0, k1, role, last, _x) in seg_recs:
         got.setdefault(wg, []).append((seq, tile, k0, k1, role, last))
-    for x, lst in enumerate(segs):
-        mine = [r[1:] for r in sorted(got.get(x, []))]
-        want = [(s.tile, s.k_begin, s.k_end, s.role, s.peers[-1] if s.peers else -1) for s in lst]
-        assert mine == want, f"workgroup {x}: {mine[:4]} != {want[:4]}"
+    dyn = not static_dp and plan.sched != S.SK_SCHED_DP and plan.dp_tiles > plan.grid
+
+    def rec(sg):
+        return (sg.tile, sg.k_begin, sg.k_end, sg.role, sg.peers[-1] if sg.peers else -1)
+    if dyn:
+        dp_got = sorted(r[1] for lst in got.values() for r in lst if r[4] == O.ROLE_DP)
+        dp_want = sorted(sg.tile for lst in segs for sg in lst if sg.role == O.ROLE_DP)
+        assert dp_got == dp_want, "data-parallel tiles differ from the oracle's or repeat"
+        for x, lst in enumerate(segs):
+            mine = [r[1:] for r in sorted(got.get(x, []))]
+            mine_sk = [r for r in mine if r[3] != O.ROLE_DP]
+            want_sk = [rec(sg) for sg in lst if sg.role != O.ROLE_DP]
+            assert mine_sk == want_sk, f"workgroup {x}: {mine_sk[:4]} != {want_sk[:4]}"
+            mine_dp = [r for r in mine if r[3] == O.ROLE_DP]
+            want_dp = [rec(sg) for sg in lst if sg.role == O.ROLE_DP]
+            assert mine_dp[:1] == want_dp[:1], f"workgroup {x}: first data-parallel tile"
+    else:
+        for x, lst in enumerate(segs):
+            mine = [r[1:] for r in sorted(got.get(x, []))]
+            want = [rec(sg) for sg in lst]
+            assert mine == want, f"workgroup {x}: {mine[:4]} != {want[:4]}"
     split = {}
     for lst in segs:
         for sg in lst:

@@ -60,20 +60,23 @@ SHAPES = [(64 * (1 + (7 * i) % 9), 64 * (1 + (5 * i) % 7), 128 * (1 + (3 * i) % 
          [(0, 64, 128), (192, 0, 256)]          # empty problems are allowed in a batch
 
 
-@pytest.mark.parametrize("sched,grid,slots", [("sk", 0, 0), ("sk", 37, 0), ("dp", 0, 0),
-                                              ("2tsk", 0, 16), ("dp1sk", 0, 16), ("auto", 0, 0)])
-def test_grouped_integer_exact_and_trace(sched, grid, slots):
-    say(f"grouped sched={sched} grid={grid} slots={slots}")
+@pytest.mark.parametrize("sched,grid,slots,flags", [("sk", 0, 0, 0), ("sk", 37, 0, 0), ("dp", 0, 0, 0),
+                                                    ("2tsk", 0, 16, 0), ("dp1sk", 0, 16, 0), ("auto", 0, 0, 0),
+                                                    ("2tsk", 0, 16, S.SK_FLAG_STATIC_DP_TILES),
+                                                    ("dp1sk", 0, 16, S.SK_FLAG_STATIC_DP_TILES)])
+def test_grouped_integer_exact_and_trace(sched, grid, slots, flags):
+    say(f"grouped sched={sched} grid={grid} slots={slots} flags={flags}")
     probs = make_batch(SHAPES, "bf16", "f32", "int4", 10)
     tr = torch.zeros(8 + 8 * 8192, dtype=torch.int32, device="cuda")
-    cfg = S.make_config(sched=sched, blk=(128, 128, 64), grid=grid, wg_slots=slots,
+    cfg = S.make_config(sched=sched, blk=(128, 128, 64), grid=grid, wg_slots=slots, flags=flags,
                         trace_ptr=tr.data_ptr(), trace_capacity=8192)
     ws = R.Workspace("cuda")
     plan, raw = R.gemm_grouped([p["d"] for p in probs], cfg=cfg, ws=ws)
     torch.cuda.synchronize()
     ws.check()
     check_results(probs, "bf16", "f32", "int4")
-    compare_trace(R.read_trace(tr), plan, [(p["m"], p["n"], p["k"]) for p in probs])
+    compare_trace(R.read_trace(tr), plan, [(p["m"], p["n"], p["k"]) for p in probs],
+                  static_dp=bool(flags & S.SK_FLAG_STATIC_DP_TILES))
 
 
 @pytest.mark.parametrize("sched", ["sk", "dp"])
@@ -147,4 +150,44 @@ def test_grouped_hipgraph_replays_match_eager():
         torch.cuda.synchronize()
         for i, p in enumerate(probs):
             assert torch.equal(p["C"].view(torch.int32), eager[i].view(torch.int32)), f"replay {rep} problem {i}"
+    del keep
+
+
+@pytest.mark.parametrize("slots", [16, 32])
+def test_grouped_dp_tile_queues_same_bits_and_replays(slots):
+    # a persistent two-tile hybrid takes its data-parallel tiles after the
+    # first wave from the per-XCD queues: the same bits as the static order,
+    # eagerly and on every graph replay (the last workgroup of each launch
+    # returns the queue counters to zero)
+    probs = make_batch(SHAPES, "bf16", "f32", "normal", 70)
+    descs = [p["d"] for p in probs]
+    ws = R.Workspace("cuda")
+    static = S.make_config(sched="2tsk", blk=(128, 128, 64), wg_slots=slots, flags=S.SK_FLAG_STATIC_DP_TILES)
+    R.gemm_grouped(descs, cfg=static, ws=ws)
+    torch.cuda.synchronize()
+    ws.check()
+    ref = [p["C"].clone() for p in probs]
+    dyn = S.make_config(sched="2tsk", blk=(128, 128, 64), wg_slots=slots)
+    plan, keep0 = R.gemm_grouped(descs, cfg=dyn, ws=ws)
+    torch.cuda.synchronize()
+    ws.check()
+    assert plan.dp_tiles > plan.grid
+    for i, p in enumerate(probs):
+        assert torch.equal(p["C"].view(torch.int32), ref[i].view(torch.int32)), f"problem {i}"
+    del keep0          # its pinned descriptor block is reused inside the capture
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        _, keep = R.gemm_grouped(descs, cfg=dyn, ws=ws, stream=stream)
+    for rep in range(3):
+        for p in probs:
+            p["C"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            assert torch.equal(p["C"].view(torch.int32), ref[i].view(torch.int32)), f"replay {rep} problem {i}"
+    ws.check()
+    words = ws.buf[:44].view(torch.int32).cpu().tolist()
+    assert words[0] == 0 and words[2] == 0 and words[3:11] == [0] * 8, words
     del keep

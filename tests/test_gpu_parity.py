@@ -72,7 +72,8 @@ def check_case(m, n, k, ab, ct, *, dist, seed=0, a_order="row", b_order="row", c
         say(f"  rel err {err:.3e} (bound {bound:.3e})")
         assert err <= bound
     if tr is not None:
-        compare_trace(tr, plan, [(m, n, k)], c_order, acc_bytes=8 if ab == "f64" else 4)
+        compare_trace(tr, plan, [(m, n, k)], c_order, acc_bytes=8 if ab == "f64" else 4,
+                      static_dp=bool(cfg is not None and cfg.flags & S.SK_FLAG_STATIC_DP_TILES))
     return Ct, plan
 
 
@@ -148,13 +149,16 @@ def test_alpha_beta_integer_exact(ab, ct, ws):
 
 @pytest.mark.parametrize("sched", ["2tsk", "dp1sk", "auto"])
 @pytest.mark.parametrize("slots", [4, 8, 13])
-def test_hybrids_on_few_slots(sched, slots, ws):
+@pytest.mark.parametrize("flags", [0, S.SK_FLAG_STATIC_DP_TILES])
+def test_hybrids_on_few_slots(sched, slots, flags, ws):
     # wg_slots below the machine's capacity exercises full DP waves plus a
-    # Stream-K region on a small problem (t = 5 x 7 = 35 tiles of 64 x 64)
+    # Stream-K region on a small problem (t = 5 x 7 = 35 tiles of 64 x 64);
+    # the data-parallel tiles after the first wave come from the per-XCD
+    # queues, or in the static order with SK_FLAG_STATIC_DP_TILES
     m, n, k = 320, 448, 320
-    cfg = S.make_config(sched=sched, blk=(64, 64, 16), wg_slots=slots)
+    cfg = S.make_config(sched=sched, blk=(64, 64, 16), wg_slots=slots, flags=flags)
     check_case(m, n, k, "f64", "f64", dist="int4", cfg=cfg, ws=ws)
-    cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots)
+    cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots, flags=flags)
     check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
 
 
