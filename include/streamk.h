@@ -156,8 +156,9 @@ typedef struct {
 
 #define SK_FLAG_NO_XCD_REMAP 0x1     /* keep logical workgroup id == hardware id */
 #define SK_FLAG_ROW_MAJOR_TILES 0x2  /* tile t -> (t / tiles_n, t % tiles_n) instead of banded order */
-/* A persistent launch with more data-parallel tiles than workgroups gives
- * workgroup x the data-parallel tile x first, then takes the others from
+/* A persistent launch of several problems (sk_gemm_grouped, count > 1) with
+ * more data-parallel tiles than workgroups gives workgroup x the
+ * data-parallel tile x first, then takes the others from
  * eight per-XCD queues (contiguous eighths of the remaining tiles, each in
  * order, an emptied queue taking from the next XCDs' ones), so uneven
  * tiles (grouped problems of different k) balance over the workgroups; the

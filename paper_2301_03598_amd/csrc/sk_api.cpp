@@ -840,7 +840,11 @@ Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws
     P.xcd_remap = pl.xcd_remap;
     P.band = (cfg && (cfg->flags & SK_FLAG_ROW_MAJOR_TILES)) ? 1 : kTileBand;
     P.fixup = pl.fixup == SK_FIXUP_SPREAD ? FIXUP_SPREAD : FIXUP_SERIAL;
-    P.dyn_dp = (pl.sched != SK_SCHED_DP && pl.dp_tiles > pl.grid &&
+    // per-XCD tile queues for batches of several problems (tiles of
+    // different cost); a single GEMM's equal tiles keep the static order,
+    // which measured faster for them (FP16 sweep, 128x128 tiles: DP +
+    // one-tile SK 327 vs 316 TFLOP/s, two-tile SK + DP 317 vs 313)
+    P.dyn_dp = (c.probs.size() > 1 && pl.sched != SK_SCHED_DP && pl.dp_tiles > pl.grid &&
                 !(cfg && (cfg->flags & SK_FLAG_STATIC_DP_TILES))) ? 1 : 0;
     P.wait_ticks = wait_ticks(cfg);
     char *w = (char *)ws;

@@ -1346,25 +1346,35 @@ __device__ __forceinline__ int tile_of_iter(const Params &p, int it) {
     }
 }
 
-// The next data-parallel tile of a persistent launch after its first wave
-// (tiles [0, g) go to workgroups 0..g-1): the tiles [g, dp_tiles) form eight
+// Data-parallel tiles of a persistent launch after its first wave (tiles
+// [0, g) go to workgroups 0..g-1): the tiles [g, dp_tiles) form eight
 // contiguous chunks, one per XCD, each taken in order through its own
 // counter, so the workgroups of one XCD keep neighbouring tiles (shared A
 // and B panels) in flight as a one-workgroup-per-tile launch does, while a
 // workgroup that drew short tiles simply takes more of them.  A workgroup
-// whose XCD's chunk is used up takes from the next XCDs' chunks.  Returns
-// an index into [0, dp_tiles - g), or dp_tiles - g when none is left.
-__device__ __forceinline__ int next_dp_tile(const Params &p, int xcd) {
-    const int D = p.dp_tiles - p.g;
-    for (int i = 0; i < XCDS; ++i) {
-        const int c = (xcd + i) % XCDS;
-        const int lo = (int)((int64_t)D * c / XCDS), hi = (int)((int64_t)D * (c + 1) / XCDS);
-        if (lo >= hi) continue;
-        const int v = __hip_atomic_fetch_add(p.hdr + HDR_NEXT + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v < hi - lo) return lo + v;
+// whose chunk is used up moves on to the next XCDs' chunks.  Thread 0 takes
+// a ticket as a tile starts (take) and resolves it after the tile's
+// epilogue (resolve), so the atomic's latency hides under the MAC loop.
+struct DpQueue {
+    // qs: workgroup-shared {chunk tickets are taken from, chunks given up as
+    // used up (8: none left)} -- shared memory, so the state costs the
+    // persistent loop no registers; ticket: that of the running tile
+    __device__ __forceinline__ static int take(const Params &p, const int *qs) {
+        return __hip_atomic_fetch_add(p.hdr + HDR_NEXT + qs[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    return D;
-}
+    // index into [0, dp_tiles - g) of the next tile, or dp_tiles - g
+    __device__ __forceinline__ static int resolve(const Params &p, int *qs, int ticket) {
+        const int D = p.dp_tiles - p.g;
+        while (qs[1] < XCDS) {
+            const int c = qs[0];
+            const int lo = (int)((int64_t)D * c / XCDS), hi = (int)((int64_t)D * (c + 1) / XCDS);
+            if (ticket < hi - lo) return lo + ticket;
+            qs[0] = (c + 1) % XCDS;
+            if (++qs[1] < XCDS) ticket = take(p, qs);
+        }
+        return D;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // the kernel body
@@ -1393,6 +1403,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     __shared__ __attribute__((aligned(16))) char lds2[C::NSTAGE >= 3 ? C::STAGE : 16];
     __shared__ __attribute__((aligned(16))) char lds3[C::NSTAGE >= 4 ? C::STAGE : 16];
     __shared__ int next_dp;     // the next queued data-parallel tile, for all waves
+    __shared__ int dp_queue[2]; // DpQueue state (thread 0 only)
     const LdsBufs bufs{lds0, lds1, lds2, lds3};
     const int tid0 = threadIdx.x;
     const int b = blockIdx.x;
@@ -1429,11 +1440,14 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     int phase = 0;         // 0, 1: the two phases; 2: done
     int seq = 0;
     const bool dp_first = DP_ONLY || p.dp_first;
-    // data-parallel tiles after the first from the per-XCD queues: thread 0
-    // takes the next one as a tile starts (the atomic's latency hides under
-    // the MAC loop) and hands it to the workgroup after the epilogue
+    // data-parallel tiles after the first from the per-XCD queues (DpQueue):
+    // thread 0 hands the next one to the workgroup after each epilogue
     const bool dyn = !DP_ONLY && p.dyn_dp;
-    int queued = 0;
+    int ticket = 0;
+    if (dyn && tid0 == 0) {
+        dp_queue[0] = b % XCDS;
+        dp_queue[1] = 0;
+    }
     while (true) {
         const bool dp_now = (phase == 0) == dp_first;
         int tile, k0, k1;
@@ -1443,7 +1457,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
             if (j >= p.dp_tiles) { ++phase; continue; }
             tile = j < p.sk_tile_begin ? j : j - p.sk_tile_begin + p.sk_tile_end;
             if (dyn) {
-                if (tid0 == 0) queued = next_dp_tile(p, b % XCDS);
+                if (tid0 == 0) ticket = DpQueue::take(p, dp_queue);
             } else {
                 j += p.g;
             }
@@ -1506,7 +1520,7 @@ __device__ __forceinline__ void sk_body(const Params &p) {
         trace_rec(p, x, seq++, tile, k0, k1, dp_now ? ROLE_DP : (ended ? ROLE_FULL : ROLE_OWNER), last, 0,
                   tid);
         if (dp_now && dyn) {
-            if (tid0 == 0) next_dp = queued;
+            if (tid0 == 0) next_dp = DpQueue::resolve(p, dp_queue, ticket);
             __syncthreads();
             j = p.g + next_dp;
             __syncthreads();

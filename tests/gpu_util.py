@@ -116,9 +116,10 @@ ROLE_REDUCE = 4
 
 def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4, static_dp=False):
     """The executed segments must be the schedule oracle's, record by record.
-    A persistent launch with more data-parallel tiles than workgroups takes
-    them, after each workgroup's first, from per-XCD queues (unless
-    SK_FLAG_STATIC_DP_TILES, `static_dp`): then each workgroup's Stream-K
+    A persistent launch of several problems with more data-parallel tiles
+    than workgroups takes them, after each workgroup's first, from per-XCD
+    queues (unless SK_FLAG_STATIC_DP_TILES, `static_dp`): then each
+    workgroup's Stream-K
     segments and first data-parallel tile are the oracle's, and the
     data-parallel tiles, whichever workgroup ran them, are the oracle's, each
     exactly once.  Slice reductions of the spread fixup (role 4) are checked
@@ -133,7 +134,7 @@ def compare_trace(trace, plan, shapes, c_order="row", acc_bytes=4, static_dp=Fal
     got = {}
     for (wg, seq, tile, k0, k1, role, last, _x) in seg_recs:
         got.setdefault(wg, []).append((seq, tile, k0, k1, role, last))
-    dyn = not static_dp and plan.sched != S.SK_SCHED_DP and plan.dp_tiles > plan.grid
+    dyn = not static_dp and len(shapes) > 1 and plan.sched != S.SK_SCHED_DP and plan.dp_tiles > plan.grid
 
     def rec(sg):
         return (sg.tile, sg.k_begin, sg.k_end, sg.role, sg.peers[-1] if sg.peers else -1)

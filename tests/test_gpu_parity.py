@@ -149,16 +149,13 @@ def test_alpha_beta_integer_exact(ab, ct, ws):
 
 @pytest.mark.parametrize("sched", ["2tsk", "dp1sk", "auto"])
 @pytest.mark.parametrize("slots", [4, 8, 13])
-@pytest.mark.parametrize("flags", [0, S.SK_FLAG_STATIC_DP_TILES])
-def test_hybrids_on_few_slots(sched, slots, flags, ws):
+def test_hybrids_on_few_slots(sched, slots, ws):
     # wg_slots below the machine's capacity exercises full DP waves plus a
-    # Stream-K region on a small problem (t = 5 x 7 = 35 tiles of 64 x 64);
-    # the data-parallel tiles after the first wave come from the per-XCD
-    # queues, or in the static order with SK_FLAG_STATIC_DP_TILES
+    # Stream-K region on a small problem (t = 5 x 7 = 35 tiles of 64 x 64)
     m, n, k = 320, 448, 320
-    cfg = S.make_config(sched=sched, blk=(64, 64, 16), wg_slots=slots, flags=flags)
+    cfg = S.make_config(sched=sched, blk=(64, 64, 16), wg_slots=slots)
     check_case(m, n, k, "f64", "f64", dist="int4", cfg=cfg, ws=ws)
-    cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots, flags=flags)
+    cfg = S.make_config(sched=sched, blk=(128, 128, 64), wg_slots=slots)
     check_case(720, 1040, 512, "bf16", "f32", dist="int4", cfg=cfg, ws=ws)
 
 
