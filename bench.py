@@ -248,25 +248,19 @@ def schedule_leg(sweep, cfg, passes=2):
 
 
 def fixed_split_configs(sweep, blk):
-    """Algorithm 4 (fixed split) as Stream-K with g = s t (section 4): per
-    problem, s is the largest divisor of the tile's iteration count I with
-    s t <= p (one wave on the resident slots) and s - 1 <= SK_MAX_PEERS, so
-    every tile is split into s equal k-ranges, one workgroup each."""
+    """Algorithm 4 (fixed split, SK_SCHED_FIXED_SPLIT) per problem with the
+    library's splitting factor: the largest s <= SK_MAX_PEERS + 1 with s t <= p
+    (one wave on the resident slots) whose pieces of ceil(I / s) iterations
+    leave none empty; s = 1 (the tiles alone fill the slots) is the
+    data-parallel schedule of the same tile."""
     from paper_2301_03598_amd import streamk as S
     out, splits = [], []
-    for (m, n, k), d in zip(sweep.shapes, sweep.descs):
-        st, pl = S.sk_plan(d, S.make_config(sched="sk", blk=blk))
+    for d in sweep.descs:
+        cfg = S.make_config(sched="fs", blk=blk)
+        st, pl = S.sk_plan(d, cfg)
         S.check(st, "sk_plan")
-        t, p = pl.tiles, pl.wg_slots
-        I = -(-k // blk[2])
-        s = 1
-        for cand in range(1, min(I, S.SK_MAX_PEERS + 1) + 1):
-            if I % cand == 0 and cand * t <= p:
-                s = cand
-        splits.append(s)
-        # s = 1 (the tiles alone fill the slots, or I has no divisor that
-        # fits): no split, the data-parallel schedule of the same tile
-        out.append(S.make_config(sched="sk", blk=blk, grid=s * t) if s > 1 else S.make_config(sched="dp", blk=blk))
+        splits.append(pl.split if pl.sched == S.SK_SCHED_FIXED_SPLIT else 1)
+        out.append(cfg)
     return out, splits
 
 
@@ -662,7 +656,7 @@ def main():
             res, tf_leg, run_leg = schedule_leg(sweep, S.make_config(sched=sched, blk=blk))
             legs[name] = (res, tf_leg)
             del run_leg
-        # Algorithm 4 as Stream-K with g = s t
+        # Algorithm 4 (fixed split) with the library's splitting factor per problem
         fs_cfgs, splits = fixed_split_configs(sweep, blk)
         res, tf_leg, run_leg = schedule_leg(sweep, fs_cfgs)
         res["split_histogram"] = {str(v): splits.count(v) for v in sorted(set(splits))}

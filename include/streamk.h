@@ -48,13 +48,20 @@ typedef enum { SK_F64 = 0, SK_F32 = 1, SK_F16 = 2, SK_BF16 = 3, SK_F8_E4M3 = 4 }
 
 /* Work decompositions (paper sections 3.2, 4 and 5.2). */
 typedef enum {
-    SK_SCHED_AUTO = 0,          /* library default, measured on MI355X: basic SK while t <= CUs, else DP
-                                   (a single GEMM whose model grid is one workgroup per tile: DP);
-                                   F64: the two-tile SK + DP hybrid */
+    SK_SCHED_AUTO = 0,          /* library default, measured on MI355X: per problem a tile and one of
+                                   the schedules below -- Stream-K while t <= CUs (for a single
+                                   16-bit or F8 GEMM on 128x128 tiles preferably the fixed split that
+                                   fills at least half of the slots), else DP, with DP + one-tile SK
+                                   for a short last wave of 256x256 tiles; F64: the two-tile SK + DP
+                                   hybrid */
     SK_SCHED_DP = 1,            /* data-parallel: one workgroup per output tile (Algorithm 2) */
     SK_SCHED_SK = 2,            /* basic Stream-K over all tiles (Algorithm 5), g from the model */
     SK_SCHED_DP_1TILE_SK = 3,   /* full DP waves, then SK over the remaining tiles on g = p */
-    SK_SCHED_2TILE_SK_DP = 4    /* SK over r + p tiles first (1..2 tiles per WG), then DP waves */
+    SK_SCHED_2TILE_SK_DP = 4,   /* SK over r + p tiles first (1..2 tiles per WG), then DP waves */
+    SK_SCHED_FIXED_SPLIT = 5    /* fixed split (Algorithm 4): s workgroups per tile, workgroup
+                                   x s + y running iterations [y ceil(I/s), min(I, (y+1) ceil(I/s)))
+                                   of tile x, g = s t; single GEMMs only (grouped calls:
+                                   SK_ERR_UNSUPPORTED) */
 } sk_sched_t;
 
 /*
@@ -138,6 +145,11 @@ typedef struct {
  *                   of the grid model: every workgroup of a plan that splits
  *                   tiles is charged 2 BM BN acc_bytes / model_bw for writing
  *                   and reading back its partial tile; 0 = no memory term.
+ *  split            SK_SCHED_FIXED_SPLIT's splitting factor s (1..SK_MAX_PEERS
+ *                   + 1, s t <= wg_slots: all s t workgroups co-resident);
+ *                   0 = the largest such s that leaves no workgroup without
+ *                   iterations.  s = 1 is the data-parallel schedule.  A
+ *                   nonzero grid must equal s t.
  */
 typedef struct {
     int32_t sched;
@@ -152,6 +164,7 @@ typedef struct {
     int32_t wait_limit_us;
     int32_t fixup;
     double model_bw;
+    int32_t split;
 } sk_config_t;
 
 #define SK_FLAG_NO_XCD_REMAP 0x1     /* keep logical workgroup id == hardware id */
@@ -198,6 +211,7 @@ typedef struct {
     uint64_t workspace_bytes;
     int32_t fixup;            /* resolved sk_fixup_t (never AUTO) */
     int32_t max_peers;        /* largest peer count of any tile's owner */
+    int32_t split;            /* SK_SCHED_FIXED_SPLIT: its s; otherwise 0 */
 } sk_plan_t;
 
 /* Plan the call without launching it: the schedule (sections 3.2, 4, 5.2),

@@ -185,25 +185,32 @@ constexpr int64_t kTailNum = 3, kTailDen = 10;
 constexpr int64_t kMidBigLo = 4, kMidBigDp = 5, kMidBigDen = 8;
 constexpr int64_t kMidBigSkIters = 48;
 
-// k-aligned Stream-K split: s workgroups per tile, each an equal k-range,
-// for the largest s <= SK_MAX_PEERS + 1 that divides the tile's iteration
-// count I with s t <= p; used when it keeps at least half of the slots busy
-// (2 s t >= p).  The paper's even split over the model's grid starts the
-// workgroups of neighbouring tiles at unrelated k offsets, so concurrently
-// running workgroups share no operand k-slices in their XCD's L2; with equal
-// k-ranges those of the same range index run the same k-slices together.
-// Measured (FP16, 128x128 tiles, t <= CUs, k >= 4096): the summed time of
-// the problems with 2 s t >= p falls by 9-27 % against the model's grid
-// (by more the closer s t comes to p); with fewer busy slots the model's
-// grid wins.  FP8 (128x128x128): 2048x1664x4096 594 -> 935 TFLOP/s,
-// 3072x1280x6144 761 -> 1263, 1152x2560x8192 657 -> 1123.  Single GEMMs
-// only (a grouped call's tiles differ in I).
-int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p) {
+// Fixed split (Algorithm 4) of t tiles of I iterations on p slots: the
+// largest s <= SK_MAX_PEERS + 1 with s t <= p whose pieces of ceil(I / s)
+// iterations leave none of the s empty; 1 if there is none.
+int64_t fixed_split_factor(int64_t tiles, int64_t iters_per_tile, int p) {
     int64_t best = 1;
     const int64_t smax = std::min<int64_t>(iters_per_tile, SK_MAX_PEERS + 1);
     for (int64_t s = 2; s <= smax; ++s)
-        if (iters_per_tile % s == 0 && s * tiles <= p) best = s;
-    return (best >= 2 && 2 * best * tiles >= p) ? best : 1;
+        if (s * tiles <= p && (s - 1) * ((iters_per_tile + s - 1) / s) < iters_per_tile) best = s;
+    return best;
+}
+
+// k-aligned split for the automatic schedule: the fixed split above, used
+// when it keeps at least half of the slots busy (2 s t >= p).  The paper's
+// even split over the model's grid starts the workgroups of neighbouring
+// tiles at unrelated k offsets, so concurrently running workgroups share no
+// operand k-slices in their XCD's L2; with a fixed split, the workgroups of
+// the same piece index run the same k-slices together.  Measured (FP16,
+// 128x128 tiles, t <= CUs, k >= 4096): the summed time of the problems with
+// 2 s t >= p (s dividing I) falls by 9-27 % against the model's grid (by
+// more the closer s t comes to p); with fewer busy slots the model's grid
+// wins.  FP8 (128x128x128): 2048x1664x4096 594 -> 894 TFLOP/s,
+// 3072x1280x6144 761 -> 1242, 1152x2560x8192 657 -> 1106.  Single GEMMs
+// only (a grouped call's tiles differ in I).
+int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p) {
+    const int64_t s = fixed_split_factor(tiles, iters_per_tile, p);
+    return (s >= 2 && 2 * s * tiles >= p) ? s : 1;
 }
 
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
@@ -394,7 +401,8 @@ struct Call {
 sk_status_t build_call(const sk_gemm_desc_t *d, int32_t count, const sk_config_t *cfg, bool grouped,
                        Call *c) {
     if (!d || count <= 0) return SK_ERR_INVALID_VALUE;
-    if (cfg && (cfg->wg_slots < 0 || cfg->grid < 0 || cfg->sched < SK_SCHED_AUTO || cfg->sched > SK_SCHED_2TILE_SK_DP))
+    if (cfg && (cfg->wg_slots < 0 || cfg->grid < 0 || cfg->split < 0 || cfg->sched < SK_SCHED_AUTO ||
+                cfg->sched > SK_SCHED_FIXED_SPLIT))
         return SK_ERR_INVALID_VALUE;
     for (int i = 0; i < count; ++i) {
         sk_status_t s = validate(d[i]);
@@ -505,7 +513,8 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     pl->iters_total = c.iters;
     pl->fixup = SK_FIXUP_SERIAL;
     int sched = cfg ? cfg->sched : SK_SCHED_AUTO;
-    if (sched < SK_SCHED_AUTO || sched > SK_SCHED_2TILE_SK_DP) return SK_ERR_INVALID_VALUE;
+    if (sched < SK_SCHED_AUTO || sched > SK_SCHED_FIXED_SPLIT) return SK_ERR_INVALID_VALUE;
+    if (cfg && cfg->split < 0) return SK_ERR_INVALID_VALUE;
     const bool auto_sched = sched == SK_SCHED_AUTO;
     const int user_grid = cfg ? cfg->grid : 0;
     if (user_grid < 0 || user_grid > SK_MAX_GRID) return SK_ERR_INVALID_VALUE;
@@ -549,6 +558,42 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         if (user_grid > p) return SK_ERR_INVALID_VALUE;   // all workgroups must be co-resident
     }
     const int pg = std::min(p, SK_MAX_GRID);   // grids the model may choose
+    // Algorithm 4: s workgroups per tile, piece y of tile x on workgroup x s + y
+    auto plan_fixed_split = [&](int64_t split) -> sk_status_t {
+        if (c.probs.size() != 1) return SK_ERR_UNSUPPORTED;
+        const int64_t I = c.imax;
+        const int64_t sp = split > 0 ? split : fixed_split_factor(t, I, pg);
+        if (sp > SK_MAX_PEERS + 1) return SK_ERR_UNSUPPORTED;
+        if (user_grid > 0 && user_grid != sp * t) return SK_ERR_INVALID_VALUE;
+        if (sp == 1) {
+            // s = 1 is the data-parallel schedule (any number of tiles)
+            pl->sched = SK_SCHED_DP;
+            pl->grid = (int32_t)t;
+            pl->dp_first = 1;
+            pl->dp_tiles = t;
+            return SK_OK;
+        }
+        if (sp * t > pg) return SK_ERR_INVALID_VALUE;   // all s t workgroups must be co-resident
+        const int64_t ips = cdiv(I, sp);
+        pl->sched = SK_SCHED_FIXED_SPLIT;
+        pl->split = (int32_t)sp;
+        pl->grid = (int32_t)(sp * t);
+        pl->sk_tile_begin = 0;
+        pl->sk_tile_end = t;
+        pl->sk_iter_begin = 0;
+        pl->sk_iters = c.iters;
+        pl->dp_tiles = 0;
+        pl->dp_first = 0;
+        pl->max_peers = (int32_t)(cdiv(I, ips) - 1);
+        pl->fixup = fix_req == SK_FIXUP_AUTO ? (pl->max_peers >= kSpreadMinPeers ? SK_FIXUP_SPREAD : SK_FIXUP_SERIAL)
+                                             : fix_req;
+        // as for deep-k basic Stream-K: with 8 or more pieces per tile the
+        // round-robin XCD placement puts equal pieces of different tiles on
+        // one XCD
+        if (pl->xcd_remap && sp >= 8) pl->xcd_remap = 0;
+        return SK_OK;
+    };
+    if (sched == SK_SCHED_FIXED_SPLIT) return plan_fixed_split(cfg ? cfg->split : 0);
     // basic Stream-K over every tile: the model's grid for a fixup mode, and
     // its predicted time
     auto sk_grid = [&](bool spread, double *val) {
@@ -570,7 +615,6 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         return gs;
     };
     int fix = SK_FIXUP_SERIAL;
-    int64_t aligned_s = 1;     // > 1: the automatic schedule's k-aligned split
     if (sched == SK_SCHED_AUTO) {
         // Measured on MI355X: Stream-K pays off while the tiles give no CU
         // more than one workgroup (t <= CUs: a lone workgroup leaves its
@@ -601,10 +645,12 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             // any other model grid of a 16-bit 128x128 problem gives way to
             // a k-aligned split that fills half of the slots
             int f0 = 0;
-            if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t)
+            if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t) {
                 sched = SK_SCHED_DP;
-            else if ((half || c.key.ab_type == SK_F8_E4M3) && single && user_grid == 0 && c.tile.bm == 128)
-                aligned_s = aligned_split(t, c.imax, pg);
+            } else if ((half || c.key.ab_type == SK_F8_E4M3) && single && user_grid == 0 && c.tile.bm == 128) {
+                const int64_t s_al = aligned_split(t, c.imax, pg);
+                if (s_al > 1) return plan_fixed_split(s_al);
+            }
         } else {
             sched = SK_SCHED_DP;
             const int64_t tail = t % p;
@@ -629,8 +675,8 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         sched = SK_SCHED_SK;
         skb = 0;
         ske = t;
-        model_g = user_grid == 0 && aligned_s == 1;
-        g = model_g ? sk_model(&fix) : (aligned_s > 1 ? aligned_s * t : user_grid);
+        model_g = user_grid == 0;
+        g = model_g ? sk_model(&fix) : user_grid;
     } else if (r == 0) {
         // perfect quantisation: data-parallel waves only
         sched = SK_SCHED_DP_1TILE_SK;
@@ -728,6 +774,7 @@ bool plan_key(const sk_gemm_desc_t &d, const sk_config_t *cfg, PlanKey *k) {
         k->cfg.model_c = cfg->model_c; k->cfg.model_d = cfg->model_d;
         k->cfg.fixup = cfg->fixup;
         k->cfg.model_bw = cfg->model_bw;
+        k->cfg.split = cfg->split;
     }
     return true;
 }
@@ -844,6 +891,7 @@ Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws
     // different cost); a single GEMM's equal tiles keep the static order,
     // which measured faster for them (FP16 sweep, 128x128 tiles: DP +
     // one-tile SK 327 vs 316 TFLOP/s, two-tile SK + DP 317 vs 313)
+    P.split = pl.sched == SK_SCHED_FIXED_SPLIT ? pl.split : 0;
     P.dyn_dp = (c.probs.size() > 1 && pl.sched != SK_SCHED_DP && pl.dp_tiles > pl.grid &&
                 !(cfg && (cfg->flags & SK_FLAG_STATIC_DP_TILES))) ? 1 : 0;
     P.wait_ticks = wait_ticks(cfg);

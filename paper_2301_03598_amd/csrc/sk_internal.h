@@ -91,6 +91,7 @@ struct Params {
     int32_t band;            // tile rasterisation band (1: row-major tiles)
     int32_t fixup;           // FIXUP_SERIAL or FIXUP_SPREAD
     int32_t dyn_dp;          // 1: data-parallel tiles after the first from the per-XCD queues
+    int32_t split;           // > 0: fixed split (s workgroups per tile, one problem) instead of the even split
     int64_t wait_ticks;      // bound of one fixup wait, in real-time-counter ticks (<= 0: give up at once)
     void *partials;          // partial-tile slots of BM*BN accumulators (see slot_first / slot_last)
     int32_t *flags;          // the fixed flag region, FLAG_STRIDE ints apart

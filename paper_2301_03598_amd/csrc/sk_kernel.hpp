@@ -1423,16 +1423,31 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     }
     const bool spread = !DP_ONLY && p.fixup == FIXUP_SPREAD;
     // Stream-K range of this workgroup: [beg, end) within the SK region
-    int q = 0, r = 0, beg = 0, end = 0, rq = 0;
+    // (fixed split, Algorithm 4: workgroup x runs piece x mod s of tile
+    // x / s, iterations [y ips, min(I, (y+1) ips)) with ips = ceil(I / s) --
+    // again one contiguous range of the region, so everything below holds)
+    const int fs = DP_ONLY ? 0 : p.split;
+    int q = 0, r = 0, beg = 0, end = 0, rq = 0, fI = 1, ips = 1;
     if (!DP_ONLY && p.sk_iters > 0) {
-        q = p.sk_iters / p.g;
-        r = p.sk_iters % p.g;
-        beg = x * q + (x < r ? x : r);
-        end = beg + q + (x < r ? 1 : 0);
-        rq = r * (q + 1);
+        if (fs > 0) {
+            fI = p.prob.iters;
+            ips = (fI + fs - 1) / fs;
+            const int tl = x / fs, y = x % fs;
+            beg = tl * fI + (y * ips < fI ? y * ips : fI);
+            end = tl * fI + ((y + 1) * ips < fI ? (y + 1) * ips : fI);
+        } else {
+            q = p.sk_iters / p.g;
+            r = p.sk_iters % p.g;
+            beg = x * q + (x < r ? x : r);
+            end = beg + q + (x < r ? 1 : 0);
+            rq = r * (q + 1);
+        }
     }
     // the workgroup holding region-relative iteration i
-    auto owner_of = [&](int i) { return i < rq ? i / (q + 1) : r + (i - rq) / q; };
+    auto owner_of = [&](int i) {
+        if (fs > 0) return (i / fI) * fs + (i % fI) / ips;
+        return i < rq ? i / (q + 1) : r + (i - rq) / q;
+    };
     // slices still to reduce (spread fixup): tile, first and last contributor
     int red_tile[2] = {-1, -1}, red_f[2] = {0, 0}, red_l[2] = {0, 0};
     int it = beg;          // next SK iteration

@@ -19,7 +19,7 @@ SK_OK, SK_ERR_INVALID_VALUE, SK_ERR_UNSUPPORTED, SK_ERR_WORKSPACE_TOO_SMALL, \
 # dtypes / orders / schedules
 SK_F64, SK_F32, SK_F16, SK_BF16, SK_F8_E4M3 = range(5)
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
-SK_SCHED_AUTO, SK_SCHED_DP, SK_SCHED_SK, SK_SCHED_DP_1TILE_SK, SK_SCHED_2TILE_SK_DP = range(5)
+SK_SCHED_AUTO, SK_SCHED_DP, SK_SCHED_SK, SK_SCHED_DP_1TILE_SK, SK_SCHED_2TILE_SK_DP, SK_SCHED_FIXED_SPLIT = range(6)
 SK_FLAG_NO_XCD_REMAP = 0x1
 SK_FLAG_ROW_MAJOR_TILES = 0x2
 SK_FLAG_STATIC_DP_TILES = 0x4
@@ -31,7 +31,7 @@ FIXUP_NAME = {v: k for k, v in FIXUP.items()}
 DTYPE = {"f64": SK_F64, "f32": SK_F32, "f16": SK_F16, "bf16": SK_BF16, "f8e4m3": SK_F8_E4M3}
 ORDER = {"row": SK_ROW_MAJOR, "col": SK_COL_MAJOR}
 SCHED = {"auto": SK_SCHED_AUTO, "dp": SK_SCHED_DP, "sk": SK_SCHED_SK,
-         "dp1sk": SK_SCHED_DP_1TILE_SK, "2tsk": SK_SCHED_2TILE_SK_DP}
+         "dp1sk": SK_SCHED_DP_1TILE_SK, "2tsk": SK_SCHED_2TILE_SK_DP, "fs": SK_SCHED_FIXED_SPLIT}
 SCHED_NAME = {v: k for k, v in SCHED.items()}
 
 SK_NOALLOC_SCRATCH_BYTES = 80 << 20
@@ -58,7 +58,8 @@ class sk_config_t(ctypes.Structure):
                 ("model_a", c_double), ("model_b", c_double), ("model_c", c_double),
                 ("model_d", c_double),
                 ("trace", c_void_p), ("trace_capacity", c_int64),
-                ("wait_limit_us", c_int32), ("fixup", c_int32), ("model_bw", c_double)]
+                ("wait_limit_us", c_int32), ("fixup", c_int32), ("model_bw", c_double),
+                ("split", c_int32)]
 
 
 class sk_plan_t(ctypes.Structure):
@@ -69,7 +70,7 @@ class sk_plan_t(ctypes.Structure):
                 ("sk_tile_begin", c_int64), ("sk_tile_end", c_int64),
                 ("sk_iter_begin", c_int64), ("sk_iters", c_int64),
                 ("dp_tiles", c_int64), ("workspace_bytes", c_uint64),
-                ("fixup", c_int32), ("max_peers", c_int32)]
+                ("fixup", c_int32), ("max_peers", c_int32), ("split", c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -201,8 +202,9 @@ def make_desc(m, n, k, A, B, C, *, ab_type, c_type, a_order="row", b_order="row"
 
 def make_config(sched="auto", blk=None, grid=0, wg_slots=0, threshold=0, flags=0,
                 model=None, trace_ptr=0, trace_capacity=0, fixup="auto",
-                wait_limit_us=0) -> sk_config_t:
+                wait_limit_us=0, split=0) -> sk_config_t:
     c = sk_config_t()
+    c.split = int(split)
     c.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
     c.wait_limit_us = int(wait_limit_us)
     c.sched = SCHED[sched] if isinstance(sched, str) else int(sched)

@@ -98,10 +98,14 @@ def run_gemm(m, n, k, A, B, *, c_type, c_order="row", C0=None, alpha=1.0, beta=0
 
 
 def oracle_segments(plan, shapes, c_order="row"):
-    """Per-WG segment lists the schedule oracle predicts for a library plan."""
+    """Per-WG segment lists the schedule oracle predicts for a library plan
+    (a fixed-split plan: Algorithm 4's)."""
     blk = (plan.blk_m, plan.blk_n, plan.blk_k)
     oshapes = [(n, m, k) if c_order == "col" else (m, n, k) for (m, n, k) in shapes]
     geos = [O.geometry(m, n, k, *blk) for (m, n, k) in oshapes]
+    if plan.sched == S.SK_SCHED_FIXED_SPLIT:
+        assert len(geos) == 1
+        return O.fixed_split_segments(geos[0].t, geos[0].I, plan.split)
     probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, oshapes)])
     op = O.Plan(plan.grid, plan.sk_tile_begin, plan.sk_tile_end, bool(plan.dp_first), plan.sched,
                 probs.tiles,

@@ -170,6 +170,8 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
     # a column-major C is computed as C^T = B^T A^T: the tile grid is n x m
     oshapes = [(n, m, k) if c_order == "col" else (m, n, k) for (m, n, k) in shapes]
     probs = oracle_problems(oshapes, blk)
+    if sched == S.SK_SCHED_FIXED_SPLIT or (st == S.SK_OK and pl.sched == S.SK_SCHED_FIXED_SPLIT):
+        return check_fixed_split_plan(st, pl, probs, p, grid, len(shapes), sched)
     if sched == S.SK_SCHED_AUTO:
         assert st == S.SK_OK, S.sk_status_string(st)
         osched = pl.sched if probs.tiles else S.SK_SCHED_DP
@@ -214,6 +216,39 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
     return pl
 
 
+def check_fixed_split_plan(st, pl, probs, p, grid, count, sched):
+    """A fixed-split plan (Algorithm 4) against the oracle's segments: the
+    library's automatic factor is the largest s <= SK_MAX_PEERS + 1 with
+    s t <= p and no empty piece (s = 1: the data-parallel schedule)."""
+    if count != 1:
+        assert st == S.SK_ERR_UNSUPPORTED
+        return None
+    t, I = probs.tiles, probs.Ip[0] if probs.tiles else 0
+    if t == 0:
+        assert st == S.SK_OK
+        return pl
+    cands = [s for s in range(2, min(I, S.SK_MAX_PEERS + 1) + 1)
+             if s * t <= min(p, S.SK_MAX_GRID) and (s - 1) * O.cdiv(I, s) < I]
+    s = max(cands) if cands else 1          # none: s = 1, the data-parallel schedule
+    if grid > 0 and grid != s * t:
+        assert st == S.SK_ERR_INVALID_VALUE, (st, t, I, p, grid)
+        return None
+    assert st == S.SK_OK, S.sk_status_string(st)
+    if sched == S.SK_SCHED_AUTO:
+        s = pl.split                 # the automatic schedule's own choice of s
+        assert 2 * s * t >= p and s in cands
+    if s == 1:
+        assert pl.sched == S.SK_SCHED_DP and pl.grid == t
+        return pl
+    segs = O.fixed_split_segments(t, I, s)
+    O.check_invariants(probs, O.Plan(s * t, 0, t, False, O.SCHED_SK, t, []), segs)
+    assert (pl.sched, pl.split, pl.grid, pl.sk_tile_begin, pl.sk_tile_end, pl.dp_tiles) == \
+        (S.SK_SCHED_FIXED_SPLIT, s, s * t, 0, t, 0)
+    assert pl.sk_iters == probs.total and pl.sk_iter_begin == 0
+    assert pl.max_peers == max(len(sg.peers) for lst in segs for sg in lst)
+    return pl
+
+
 def test_plan_config1_model_grid():
     pl = check_plan_agrees([(384, 384, 1024)], "f64", (128, 128, 16), 256, "sk", 0)
     assert pl.tiles == 9 and pl.iters_total == 576
@@ -223,7 +258,7 @@ def test_plan_config1_model_grid():
 @given(m=st.integers(1, 9000), n=st.integers(1, 9000), k=st.integers(1, 9000),
        dtype=st.sampled_from(["f64", "bf16", "f16", "f8e4m3"]), ti=st.integers(0, 2),
        p=st.sampled_from([8, 64, 256, 512]),
-       sched=st.sampled_from(["dp", "sk", "dp1sk", "2tsk", "auto"]),
+       sched=st.sampled_from(["dp", "sk", "dp1sk", "2tsk", "auto", "fs"]),
        grid=st.integers(0, 64), thr=st.sampled_from([0, 1, 3]),
        c_order=st.sampled_from(["row", "col"]))
 def test_plan_matches_schedule_oracle(m, n, k, dtype, ti, p, sched, grid, thr, c_order):
@@ -261,10 +296,11 @@ def test_auto_tile_and_schedule_policy():
                                     (4096, 4096 - 128, 512, 128, S.SK_SCHED_DP),
                                     (4096 + 128, 4096, 512, 256, None),
                                     (256, 256, 512, 64, None), (512, 448, 2048, 64, S.SK_SCHED_SK),
-                                    (256, 256, 65536, 128, S.SK_SCHED_SK),
-                                    (2048, 1536, 4096, 64, S.SK_SCHED_DP), (2048, 1536, 4104, 128, S.SK_SCHED_SK),
-                                    (2048, 1536 + 128, 2048, 128, S.SK_SCHED_SK),
-                                    (4096, 1024, 4096, 128, S.SK_SCHED_SK),
+                                    (256, 256, 65536, 128, S.SK_SCHED_FIXED_SPLIT),
+                                    (2048, 1536, 4096, 64, S.SK_SCHED_DP),
+                                    (2048, 1536, 4104, 128, S.SK_SCHED_FIXED_SPLIT),
+                                    (2048, 1536 + 128, 2048, 128, S.SK_SCHED_FIXED_SPLIT),
+                                    (4096, 1024, 4096, 128, S.SK_SCHED_FIXED_SPLIT),
                                     (2048, 2048 + 128, 2048, 128, S.SK_SCHED_DP)):
         st, pl = S.sk_plan(desc(m=m, n=n, k=k, ab_type="bf16", c_type="f32"), cfg)
         assert st == S.SK_OK and pl.blk_m == blk_m, (m, n, k, pl.blk_m)
@@ -276,11 +312,14 @@ def test_auto_tile_and_schedule_policy():
     # FP64 keeps its default tile (128x128x16)
     st, pl = S.sk_plan(desc(m=256, n=256, k=512, ab_type="f64", c_type="f64"), cfg)
     assert st == S.SK_OK and (pl.blk_m, pl.blk_k) == (128, 16)
-    # AUTO: basic Stream-K while t <= CUs (= wg_slots / LDS-bound workgroups per CU), else DP
+    # AUTO: Stream-K while t <= CUs (= wg_slots / LDS-bound workgroups per CU), else DP; here
+    # as the k-aligned fixed split, which fills at least half of the slots in these cases
     blk = (128, 128, 64)
     # (with wg_slots = 512 the 128x128x64 kernel's LDS allows 2 workgroups per CU: 256 CUs)
-    for (m, n, k, want) in ((1024, 1024, 8192, S.SK_SCHED_SK), (2048, 2048 - 128, 8192, S.SK_SCHED_SK),
-                            (2048, 2048, 8192, S.SK_SCHED_SK), (2048, 2048 + 128, 8192, S.SK_SCHED_DP),
+    for (m, n, k, want) in ((1024, 1024, 8192, S.SK_SCHED_FIXED_SPLIT),
+                            (2048, 2048 - 128, 8192, S.SK_SCHED_FIXED_SPLIT),
+                            (2048, 2048, 8192, S.SK_SCHED_FIXED_SPLIT), (2048, 2048 + 128, 8192, S.SK_SCHED_DP),
+                            (256, 128, 8192, S.SK_SCHED_SK),    # 2 tiles: no split fills half the slots
                             (4096, 4096, 8192, S.SK_SCHED_DP),
                             # shallow k: the model grid is one workgroup per tile, i.e. DP
                             (1024, 1024, 512, S.SK_SCHED_DP), (2048, 2048, 512, S.SK_SCHED_DP)):
@@ -318,18 +357,21 @@ def test_auto_refinements():
     assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_DP)
     pl = plan(1280, 1280, 2048, c=c64)                 # 400 >= 384 such tiles: data-parallel
     assert (pl.blk_m, pl.tiles, pl.sched) == (64, 400, S.SK_SCHED_DP)
-    # 128x128 Stream-K: k-aligned split, s | I, s t <= p <= 2 s t
+    # 128x128 Stream-K: k-aligned fixed split, s t <= p <= 2 s t
     for (m, n, k, g) in ((2048, 1664, 2048, 416), (4096, 1024, 4096, 512), (1024, 1024, 8192, 512),
                          (128 * 9, 128 * 20, 8192, 360)):
         pl = plan(m, n, k)
-        assert (pl.blk_m, pl.sched, pl.grid) == (128, S.SK_SCHED_SK, g), (m, n, k, pl.grid)
-        assert pl.max_peers == g // pl.tiles - 1
-    # no divisor of I = 127 fills half the slots: the model's grid
+        assert (pl.blk_m, pl.sched, pl.grid) == (128, S.SK_SCHED_FIXED_SPLIT, g), (m, n, k, pl.grid)
+        assert pl.split == g // pl.tiles and pl.max_peers == pl.split - 1
+    # I = 127 has no divisor that fills half the slots: pieces of 16 (the last 15)
     pl = plan(1024, 1024, 127 * 64)
-    assert pl.sched == S.SK_SCHED_SK and pl.grid % pl.tiles != 0
+    assert (pl.sched, pl.split, pl.grid, pl.max_peers) == (S.SK_SCHED_FIXED_SPLIT, 8, 512, 7)
+    # few tiles: the model's grid (no s fills half the slots)
+    pl = plan(256, 256, 8192)
+    assert pl.sched == S.SK_SCHED_SK
     # FP8's 128x128x128 tile too
     pl = plan(2048, 1664, 4096, dt="f8e4m3")
-    assert (pl.blk_m, pl.blk_k, pl.sched, pl.grid) == (128, 128, S.SK_SCHED_SK, 416)
+    assert (pl.blk_m, pl.blk_k, pl.sched, pl.grid) == (128, 128, S.SK_SCHED_FIXED_SPLIT, 416)
     # grouped calls keep the model's grid
     d = desc(m=1024, n=1024, k=8192, ab_type="bf16", c_type="f32")
     st, pl = S.sk_plan([d, d], S.make_config(blk=(128, 128, 64), wg_slots=512))
@@ -440,3 +482,40 @@ def test_model_memory_term():
         grids[bw] = pl.grid
     assert grids[1e12] == grids[0.0]
     assert grids[1e4] < grids[4e6] <= grids[0.0]
+
+
+def test_fixed_split_plans():
+    # Algorithm 4 with s not dividing I: pieces of ceil(I / s), the last shorter
+    d = desc(m=512, n=512, k=100 * 64, ab_type="bf16", c_type="f32")          # t = 16, I = 100
+    pl = check_plan_agrees([(512, 512, 100 * 64)], "bf16", (128, 128, 64), 512, "fs", 0)
+    # automatic s: 25 (s = 26..32 would give pieces of 4 and leave empty ones)
+    assert (pl.split, pl.grid, pl.max_peers) == (25, 400, 24)
+    # an explicit s may leave empty pieces (Algorithm 4): s = 33, pieces of 4, 25 of them non-empty
+    for s_, peers in ((3, 2), (7, 6), (9, 8), (33, 24)):
+        st, pl = S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=1024, split=s_))
+        assert st == S.SK_OK and (pl.sched, pl.split, pl.grid, pl.max_peers) == \
+            (S.SK_SCHED_FIXED_SPLIT, s_, 16 * s_, peers), (s_, pl.max_peers)
+    # s = 50: pieces of 2
+    st, pl = S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=1024, split=50))
+    assert st == S.SK_OK and pl.max_peers == 49
+    # I = 9, s = 4: pieces of 3, the last empty (Algorithm 4 allows it)
+    d9 = desc(m=128, n=128, k=9 * 64, ab_type="bf16", c_type="f32")
+    st, pl = S.sk_plan(d9, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=64, split=4))
+    assert st == S.SK_OK and (pl.grid, pl.max_peers) == (4, 2)
+    # s = 1 is the data-parallel schedule, also with more tiles than slots
+    st, pl = S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=512, split=1))
+    assert st == S.SK_OK and (pl.sched, pl.grid) == (S.SK_SCHED_DP, 16)
+    dbig = desc(m=4096, n=4096, k=4096, ab_type="bf16", c_type="f32")          # t = 1024 > 512 slots
+    st, pl = S.sk_plan(dbig, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=512))
+    assert st == S.SK_OK and (pl.sched, pl.grid) == (S.SK_SCHED_DP, 1024)
+    # errors: more peers than served, more workgroups than slots, a grid
+    # other than s t, grouped calls
+    assert S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=2048, split=66))[0] == \
+        S.SK_ERR_UNSUPPORTED
+    assert S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=256, split=17))[0] == \
+        S.SK_ERR_INVALID_VALUE
+    assert S.sk_plan(d, S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=512, split=4, grid=60))[0] == \
+        S.SK_ERR_INVALID_VALUE
+    assert S.sk_plan([d, d], S.make_config(sched="fs", blk=(128, 128, 64), wg_slots=512))[0] == \
+        S.SK_ERR_UNSUPPORTED
+    assert S.sk_plan(d, S.make_config(sched="fs", split=-1))[0] == S.SK_ERR_INVALID_VALUE

@@ -50,6 +50,23 @@ def test_streamk_g_st_is_fixed_split(ab, ct, m, n, k, blk, s, fixup, ws):
     check_case(m, n, k, ab, ct, dist="int4", seed=4, cfg=cfg, ws=ws)
 
 
+@pytest.mark.parametrize("ab,ct,m,n,k,blk,s", [("bf16", "f32", 256, 384, 100 * 64, (128, 128, 64), 7),
+                                               ("bf16", "f32", 256, 384, 100 * 64, (128, 128, 64), 33),
+                                               ("f16", "f16", 208, 336, 9 * 64, (128, 128, 64), 4),
+                                               ("f64", "f64", 384, 256, 13 * 16, (128, 128, 16), 5),
+                                               ("f8e4m3", "f32", 256, 256, 11 * 128, (128, 128, 128), 3)])
+@pytest.mark.parametrize("fixup", ["serial", "spread"])
+def test_fixed_split_schedule(ab, ct, m, n, k, blk, s, fixup, ws):
+    # Algorithm 4 as its own schedule: pieces of ceil(I / s) iterations, the
+    # last shorter or empty (I = 100, s = 33: 25 non-empty pieces; I = 9,
+    # s = 4: the fourth empty); trace = the oracle's fixed_split_segments
+    cfg = S.make_config(sched="fs", blk=blk, split=s, fixup=fixup)
+    say(f"fixed split schedule {ab} {m}x{n}x{k} s={s} fixup={fixup}")
+    _, plan = check_case(m, n, k, ab, ct, dist="int4", seed=6, cfg=cfg, ws=ws)
+    geo = O.geometry(m, n, k, *blk)
+    assert (plan.sched, plan.split, plan.grid) == (S.SK_SCHED_FIXED_SPLIT, s, s * geo.t)
+
+
 def test_tuner_choice_is_exact():
     tuner = T.Tuner()
     m, n, k = 384, 640, 2048
