@@ -170,11 +170,16 @@ constexpr int64_t kTinyDpMaxK = 4096;
 //  * 256x256 tile past a full wave with a last partial wave of at most
 //    kTailNum / kTailDen of the slots and at least kDeepIters k-iterations
 //    per tile: data-parallel waves + one-tile Stream-K (section 5.2) instead
-//    of a nearly empty last data-parallel wave (2792x6064x7048: 418 -> 295 us;
-//    sweep +0.8 %).  With a fuller last wave or shallower k the partial-tile
-//    traffic of the split costs more than the idle slots.
+//    of a nearly empty last data-parallel wave, its tail as a fixed split
+//    (tail_split_factor) rather than the even split over all p workgroups,
+//    whose pieces start at unrelated k offsets (FP16: 2048x8448x7040 with an
+//    8-tile tail: DP 357, even tail 280, fixed-split tail 256 us;
+//    2048x11264x4096, 96-tile tail: 211, 209, 196; 2048x12288x4096,
+//    128-tile tail: 213, 207, 205).  With a tail of more than half the
+//    slots no split of two or more fits and DP stays.
 constexpr int64_t kDeepIters = 32;
-constexpr int64_t kTailNum = 3, kTailDen = 10;
+constexpr int64_t kTailNum = 1, kTailDen = 2;
+constexpr int64_t kTailMaxSplit = 16;
 // A single GEMM with between kMidBigDp/kMidBigDen of the CUs and all CUs in
 // 256x256 tiles and at least kDeepIters k-iterations per tile takes that
 // tile, data-parallel (the 128x128 tile would give 2-4 partial waves of one
@@ -185,6 +190,11 @@ constexpr int64_t kTailNum = 3, kTailDen = 10;
 constexpr int64_t kMidBigLo = 4, kMidBigDp = 5, kMidBigDen = 8;
 constexpr int64_t kMidBigSkIters = 48;
 
+// The fixed split of a hybrid's tail of r tiles: the largest s <= 16 with
+// s r <= p and no empty piece (1: none).  Measured on 256x256 FP16 tiles:
+// an 8-tile tail split 16 ways beat 32 ways (2048x8448x7040: 256 vs 260 us).
+int64_t tail_split_factor(int64_t r, int64_t iters_per_tile, int p);
+
 // Fixed split (Algorithm 4) of t tiles of I iterations on p slots: the
 // largest s <= SK_MAX_PEERS + 1 with s t <= p whose pieces of ceil(I / s)
 // iterations leave none of the s empty; 1 if there is none.
@@ -193,6 +203,14 @@ int64_t fixed_split_factor(int64_t tiles, int64_t iters_per_tile, int p) {
     const int64_t smax = std::min<int64_t>(iters_per_tile, SK_MAX_PEERS + 1);
     for (int64_t s = 2; s <= smax; ++s)
         if (s * tiles <= p && (s - 1) * ((iters_per_tile + s - 1) / s) < iters_per_tile) best = s;
+    return best;
+}
+
+int64_t tail_split_factor(int64_t r, int64_t iters_per_tile, int p) {
+    int64_t best = 1;
+    const int64_t smax = std::min<int64_t>(iters_per_tile, kTailMaxSplit);
+    for (int64_t s = 2; s <= smax; ++s)
+        if (s * r <= p && (s - 1) * ((iters_per_tile + s - 1) / s) < iters_per_tile) best = s;
     return best;
 }
 
@@ -615,6 +633,7 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         return gs;
     };
     int fix = SK_FIXUP_SERIAL;
+    int64_t tail_split = 0;    // > 1: the automatic hybrid's fixed-split tail
     if (sched == SK_SCHED_AUTO) {
         // Measured on MI355X: Stream-K pays off while the tiles give no CU
         // more than one workgroup (t <= CUs: a lone workgroup leaves its
@@ -655,9 +674,10 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             sched = SK_SCHED_DP;
             const int64_t tail = t % p;
             if (half && single && user_grid == 0 && c.tile.bm >= 256 && t > p && tail > 0 &&
-                kTailDen * tail <= kTailNum * (int64_t)p && c.imax >= kDeepIters &&
-                c.max_peers(c.tile_iter_begin(t - tail), c.region_iters(t - tail, t), pg) <= SK_MAX_PEERS)
-                sched = SK_SCHED_DP_1TILE_SK;
+                kTailDen * tail <= kTailNum * (int64_t)p && c.imax >= kDeepIters) {
+                tail_split = tail_split_factor(tail, c.imax, pg);
+                if (tail_split > 1) sched = SK_SCHED_DP_1TILE_SK;
+            }
         }
     }
     if (sched == SK_SCHED_DP) {
@@ -698,7 +718,20 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
     // workgroups then have an empty Stream-K range)
     if (sched == SK_SCHED_SK && sk_iters > 0) g = std::max<int64_t>(1, std::min<int64_t>(g, sk_iters));
     int64_t sk_ib = skb < t ? c.tile_iter_begin(skb) : c.iters;
-    int64_t mp = c.max_peers(sk_ib, sk_iters, g);
+    int64_t mp = 0;
+    if (sched == SK_SCHED_DP_1TILE_SK && ((cfg && cfg->split > 1) || tail_split > 1) && ske > skb) {
+        // DP + one-tile SK with a fixed-split tail (Algorithm 4 on the tail
+        // tiles): s workgroups per tail tile, k-aligned; the other
+        // workgroups run only their data-parallel tiles.  Single GEMMs.
+        if (c.probs.size() != 1) return SK_ERR_UNSUPPORTED;
+        const int64_t sp = tail_split > 1 ? tail_split : cfg->split, ips = cdiv(c.imax, sp);
+        if (sp > SK_MAX_PEERS + 1) return SK_ERR_UNSUPPORTED;
+        if (sp * (ske - skb) > g) return SK_ERR_INVALID_VALUE;
+        pl->split = (int32_t)sp;
+        mp = cdiv(c.imax, ips) - 1;
+    } else {
+        mp = c.max_peers(sk_ib, sk_iters, g);
+    }
     if (mp > SK_MAX_PEERS) {
         // only a hybrid the automatic schedule chose (or an explicit grid)
         // gets here: the automatic schedule falls back to basic Stream-K
@@ -891,7 +924,7 @@ Params make_params(const Call &c, const sk_plan_t &pl, const Layout &L, void *ws
     // different cost); a single GEMM's equal tiles keep the static order,
     // which measured faster for them (FP16 sweep, 128x128 tiles: DP +
     // one-tile SK 327 vs 316 TFLOP/s, two-tile SK + DP 317 vs 313)
-    P.split = pl.sched == SK_SCHED_FIXED_SPLIT ? pl.split : 0;
+    P.split = pl.split;
     P.dyn_dp = (c.probs.size() > 1 && pl.sched != SK_SCHED_DP && pl.dp_tiles > pl.grid &&
                 !(cfg && (cfg->flags & SK_FLAG_STATIC_DP_TILES))) ? 1 : 0;
     P.wait_ticks = wait_ticks(cfg);

@@ -1430,11 +1430,17 @@ __device__ __forceinline__ void sk_body(const Params &p) {
     int q = 0, r = 0, beg = 0, end = 0, rq = 0, fI = 1, ips = 1;
     if (!DP_ONLY && p.sk_iters > 0) {
         if (fs > 0) {
+            // (a hybrid's region of fewer than g / s tiles leaves the
+            // workgroups past s tiles without Stream-K work)
             fI = p.prob.iters;
             ips = (fI + fs - 1) / fs;
             const int tl = x / fs, y = x % fs;
-            beg = tl * fI + (y * ips < fI ? y * ips : fI);
-            end = tl * fI + ((y + 1) * ips < fI ? (y + 1) * ips : fI);
+            if (tl < p.sk_iters / fI) {
+                beg = tl * fI + (y * ips < fI ? y * ips : fI);
+                end = tl * fI + ((y + 1) * ips < fI ? (y + 1) * ips : fI);
+            } else {
+                beg = end = p.sk_iters;
+            }
         } else {
             q = p.sk_iters / p.g;
             r = p.sk_iters % p.g;

@@ -106,6 +106,20 @@ def oracle_segments(plan, shapes, c_order="row"):
     if plan.sched == S.SK_SCHED_FIXED_SPLIT:
         assert len(geos) == 1
         return O.fixed_split_segments(geos[0].t, geos[0].I, plan.split)
+    if plan.sched == S.SK_SCHED_DP_1TILE_SK and plan.split > 0:
+        # data-parallel waves (tile j on workgroup j mod g), then Algorithm 4
+        # on the tail tiles
+        assert len(geos) == 1 and plan.dp_first
+        g, I = plan.grid, geos[0].I
+        out = [[] for _ in range(g)]
+        for j in range(plan.dp_tiles):
+            out[j % g].append(O.Segment(j % g, j, 0, I, O.ROLE_DP))
+        r = plan.sk_tile_end - plan.sk_tile_begin
+        for lst in O.fixed_split_segments(r, I, plan.split):
+            for sg in lst:
+                out[sg.wg].append(O.Segment(sg.wg, plan.sk_tile_begin + sg.tile, sg.k_begin, sg.k_end,
+                                            sg.role, sg.peers))
+        return out
     probs = O.Problems([(g.t if (m > 0 and n > 0) else 0, g.I) for g, (m, n, k) in zip(geos, oshapes)])
     op = O.Plan(plan.grid, plan.sk_tile_begin, plan.sk_tile_end, bool(plan.dp_first), plan.sched,
                 probs.tiles,

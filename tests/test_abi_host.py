@@ -179,6 +179,17 @@ def check_plan_agrees(shapes, dtype, blk, p, sched, grid, threshold=0, c_order="
     else:
         osched, ogrid = sched, grid
     op = O.plan_problems(probs, p=p, sched=osched, grid=ogrid, consts=MODEL, threshold=threshold or 2)
+    if st == S.SK_OK and pl.sched == S.SK_SCHED_DP_1TILE_SK and pl.split > 0:
+        # the automatic hybrid's fixed-split tail: the oracle's region and
+        # grid, Algorithm 4 on the tail tiles
+        assert sched == S.SK_SCHED_AUTO and len(shapes) == 1
+        assert (pl.sk_tile_begin, pl.sk_tile_end, pl.grid, pl.dp_tiles) == \
+            (op.sk_tile_begin, op.sk_tile_end, op.g, len(op.dp_tiles))
+        r = pl.sk_tile_end - pl.sk_tile_begin
+        segs = O.fixed_split_segments(r, probs.Ip[0], pl.split)
+        assert 2 <= pl.split <= 16 and pl.split * r <= pl.grid
+        assert pl.max_peers == max(len(sg.peers) for lst in segs for sg in lst)
+        return pl
     if sched == S.SK_SCHED_AUTO and grid == 0 and pl.sched == S.SK_SCHED_SK and pl.grid != op.g:
         # the library's k-aligned split instead of the model's grid: s
         # workgroups per tile, s dividing the tile's iteration count, filling
@@ -391,18 +402,20 @@ def test_auto_refinements():
     d = desc(m=2048, n=2560, k=4096, ab_type="bf16", c_type="f32")
     st, pl = S.sk_plan([d, d], cfg)               # 2 x 80 256x256 tiles: not a single GEMM
     assert st == S.SK_OK and pl.blk_m == 128
-    # 256x256 past a full wave: DP waves + one-tile Stream-K when the last
-    # wave holds at most 3/10 of the slots and k has >= 32 iterations per tile
+    # 256x256 past a full wave: DP waves + one-tile Stream-K with a
+    # fixed-split tail (s <= 16 pieces per tail tile) when the last wave holds
+    # at most half of the slots and k has >= 32 iterations per tile
     c256 = S.make_config(wg_slots=256)                 # one 256x256 workgroup per CU
-    pl = plan(4096, 4096 + 256, 4096, c=c256)          # 272 tiles: 256 + 16
-    assert (pl.blk_m, pl.sched, pl.grid, pl.dp_tiles) == (256, S.SK_SCHED_DP_1TILE_SK, 256, 256)
-    assert pl.max_peers <= S.SK_MAX_PEERS
-    pl = plan(256 * 257, 256, 4096, c=c256)            # one leftover tile of 64 iterations: 63 peers
-    assert (pl.sched, pl.max_peers) == (S.SK_SCHED_DP_1TILE_SK, 63)
+    for (m, n, k, split, peers) in ((4096, 4096 + 256, 4096, 16, 15),   # 272 tiles: 256 + 16
+                                    (4096, 256 * 22, 4096, 2, 1),       # 352 tiles: a 96-tile tail
+                                    (256 * 257, 256, 4096, 16, 15),     # one leftover tile
+                                    (256 * 257, 256, 8192, 16, 15)):
+        pl = plan(m, n, k, c=c256)
+        assert (pl.blk_m, pl.sched, pl.grid, pl.dp_tiles, pl.split, pl.max_peers) == \
+            (256, S.SK_SCHED_DP_1TILE_SK, 256, 256, split, peers), (m, n, k)
     for (m, n, k) in ((4096, 4096 + 256, 1024),          # 16 iterations per tile
-                      (4096, 256 * 22, 4096),            # last wave 96 > 76.8 slots
-                      (4096, 4096, 4096),                # no partial wave
-                      (256 * 257, 256, 8192)):           # one leftover tile: 127 peers
+                      (4096, 256 * 25, 4096),            # a 144-tile tail: more than half the slots
+                      (4096, 4096, 4096)):               # no partial wave
         pl = plan(m, n, k, c=c256)
         assert (pl.blk_m, pl.sched) == (256, S.SK_SCHED_DP), (m, n, k, pl.sched)
 

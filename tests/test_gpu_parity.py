@@ -178,6 +178,20 @@ def test_default_schedule_refinements(ab, m, n, k, blk_m, sched, ws):
         assert plan.dp_tiles == plan.grid and plan.sk_tile_end - plan.sk_tile_begin == plan.tiles - plan.grid
 
 
+@pytest.mark.parametrize("ab,ct,m,n,k,blk,slots,split", [
+    ("f64", "f64", 320, 448, 320, (64, 64, 16), 8, 2),          # 35 tiles: 32 DP + 3 tail, pieces of 10
+    ("bf16", "f32", 720, 1040, 512, (128, 128, 64), 16, 2),     # 54 tiles: 48 DP + 6 tail
+    ("f16", "f16", 720, 1040, 13 * 64, (128, 128, 64), 24, 4),  # 54 = 48 + 6 tail, I = 13: pieces 4,4,4,1
+    ("f8e4m3", "f32", 720, 1040, 5 * 128, (128, 128, 128), 24, 3)])  # I = 5: pieces 2, 2, 1
+@pytest.mark.parametrize("fixup", ["serial", "spread"])
+def test_dp1sk_fixed_split_tail(ab, ct, m, n, k, blk, slots, split, fixup, ws):
+    # DP + one-tile SK with its tail as a fixed split (Algorithm 4 on the tail
+    # tiles): exact, trace = DP waves + the oracle's fixed_split_segments
+    cfg = S.make_config(sched="dp1sk", blk=blk, wg_slots=slots, split=split, fixup=fixup)
+    _, plan = check_case(m, n, k, ab, ct, dist="int4", cfg=cfg, ws=ws)
+    assert plan.sched == S.SK_SCHED_DP_1TILE_SK and plan.split == split and plan.dp_tiles > 0
+
+
 @pytest.mark.parametrize("m,n,k", [(384, 384, 64), (256, 640, 128)])
 def test_dp1sk_region_smaller_than_grid(m, n, k, ws):
     # DP + one-tile SK where the Stream-K region has fewer iterations than the
