@@ -52,8 +52,8 @@ typedef enum {
                                    the schedules below -- Stream-K while t <= CUs (for a single
                                    16-bit or F8 GEMM on 128x128 tiles preferably the fixed split that
                                    fills at least half of the slots), else DP, with DP + one-tile SK
-                                   for a short last wave of 256x256 tiles; F64: the two-tile SK + DP
-                                   hybrid */
+                                   (its tail a fixed split) for a last wave of at most half the slots
+                                   of 256x256 tiles; F64: the two-tile SK + DP hybrid */
     SK_SCHED_DP = 1,            /* data-parallel: one workgroup per output tile (Algorithm 2) */
     SK_SCHED_SK = 2,            /* basic Stream-K over all tiles (Algorithm 5), g from the model */
     SK_SCHED_DP_1TILE_SK = 3,   /* full DP waves, then SK over the remaining tiles on g = p */
@@ -149,7 +149,10 @@ typedef struct {
  *                   + 1, s t <= wg_slots: all s t workgroups co-resident);
  *                   0 = the largest such s that leaves no workgroup without
  *                   iterations.  s = 1 is the data-parallel schedule.  A
- *                   nonzero grid must equal s t.
+ *                   nonzero grid must equal s t.  With SK_SCHED_DP_1TILE_SK,
+ *                   s > 1 makes the Stream-K tail of r tiles a fixed split
+ *                   (workgroup x < s r runs piece x mod s of tail tile x / s;
+ *                   s r <= grid, single GEMMs); 0 or 1 = the even split.
  */
 typedef struct {
     int32_t sched;
@@ -211,7 +214,8 @@ typedef struct {
     uint64_t workspace_bytes;
     int32_t fixup;            /* resolved sk_fixup_t (never AUTO) */
     int32_t max_peers;        /* largest peer count of any tile's owner */
-    int32_t split;            /* SK_SCHED_FIXED_SPLIT: its s; otherwise 0 */
+    int32_t split;            /* SK_SCHED_FIXED_SPLIT: its s; SK_SCHED_DP_1TILE_SK: the
+                                 fixed-split tail's s (0: even split); otherwise 0 */
 } sk_plan_t;
 
 /* Plan the call without launching it: the schedule (sections 3.2, 4, 5.2),
