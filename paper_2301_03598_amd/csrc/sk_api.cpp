@@ -226,9 +226,12 @@ int64_t tail_split_factor(int64_t r, int64_t iters_per_tile, int p) {
 // wins.  FP8 (128x128x128): 2048x1664x4096 594 -> 894 TFLOP/s,
 // 3072x1280x6144 761 -> 1242, 1152x2560x8192 657 -> 1106.  Single GEMMs
 // only (a grouped call's tiles differ in I).
-int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p) {
+// On the 64x64 tile (four workgroups per CU) it pays from 5/8 of the slots
+// on (FP16 sweep, the 64x64 Stream-K problems with s t >= 5/8 p: -4 to
+// -6.5 %; at half of the slots +5 to +13 %).
+int64_t aligned_split(int64_t tiles, int64_t iters_per_tile, int p, int64_t fill_num, int64_t fill_den) {
     const int64_t s = fixed_split_factor(tiles, iters_per_tile, p);
-    return (s >= 2 && 2 * s * tiles >= p) ? s : 1;
+    return (s >= 2 && fill_den * s * tiles >= fill_num * (int64_t)p) ? s : 1;
 }
 
 sk_status_t resolve_tile(int ab, const sk_config_t *cfg, TileDef *out) {
@@ -667,7 +670,10 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t) {
                 sched = SK_SCHED_DP;
             } else if ((half || c.key.ab_type == SK_F8_E4M3) && single && user_grid == 0 && c.tile.bm == 128) {
-                const int64_t s_al = aligned_split(t, c.imax, pg);
+                const int64_t s_al = aligned_split(t, c.imax, pg, 1, 2);
+                if (s_al > 1) return plan_fixed_split(s_al);
+            } else if (half && single && user_grid == 0 && c.tile.bm == 64) {
+                const int64_t s_al = aligned_split(t, c.imax, pg, 5, 8);
                 if (s_al > 1) return plan_fixed_split(s_al);
             }
         } else {

@@ -306,7 +306,7 @@ def test_auto_tile_and_schedule_policy():
                                     (4096, 4096, 512, 256, None), (4096, 2048, 512, 128, S.SK_SCHED_DP),
                                     (4096, 4096 - 128, 512, 128, S.SK_SCHED_DP),
                                     (4096 + 128, 4096, 512, 256, None),
-                                    (256, 256, 512, 64, None), (512, 448, 2048, 64, S.SK_SCHED_SK),
+                                    (256, 256, 512, 64, None), (512, 448, 2048, 64, S.SK_SCHED_FIXED_SPLIT),
                                     (256, 256, 65536, 128, S.SK_SCHED_FIXED_SPLIT),
                                     (2048, 1536, 4096, 64, S.SK_SCHED_DP),
                                     (2048, 1536, 4104, 128, S.SK_SCHED_FIXED_SPLIT),
@@ -360,8 +360,12 @@ def test_auto_refinements():
     # k-iterations per tile on, one workgroup per tile below (1280 slots:
     # five 64x64 workgroups per CU by LDS, 256 CUs)
     c64 = S.make_config(wg_slots=1280)
-    pl = plan(1024, 1024, 2048, c=c64)
-    assert (pl.blk_m, pl.tiles, pl.sched) == (64, 256, S.SK_SCHED_SK) and pl.grid > 256
+    pl = plan(1024, 1024, 2048, c=c64)                 # as a fixed split filling 5/8 of the slots
+    assert (pl.blk_m, pl.tiles, pl.sched, pl.split) == (64, 256, S.SK_SCHED_FIXED_SPLIT, 4) and pl.grid > 256
+    pl = plan(1024, 640, 2048, c=c64)                  # 160 tiles: s = 6 (grids stop at SK_MAX_GRID = 1024)
+    assert (pl.blk_m, pl.sched, pl.split) == (64, S.SK_SCHED_FIXED_SPLIT, 6)
+    pl = plan(192, 192, 8192, c=c64)                   # 9 tiles: 65 x 9 < 5/8 x 1024: the model's grid
+    assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_SK)
     pl = plan(1024, 1024, 1024, c=c64)
     assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_DP)
     pl = plan(2048, 1536, 4096, c=c64)                 # 768 such tiles: data-parallel
@@ -377,9 +381,12 @@ def test_auto_refinements():
     # I = 127 has no divisor that fills half the slots: pieces of 16 (the last 15)
     pl = plan(1024, 1024, 127 * 64)
     assert (pl.sched, pl.split, pl.grid, pl.max_peers) == (S.SK_SCHED_FIXED_SPLIT, 8, 512, 7)
-    # few tiles: the model's grid (no s fills half the slots)
+    # few tiles: the model's grid (no s fills enough of the slots); 256x256
+    # (16 tiles of 64x64) fills 5/8 of them with s = 32
+    pl = plan(128, 128, 8192)
+    assert (pl.blk_m, pl.sched) == (64, S.SK_SCHED_SK)
     pl = plan(256, 256, 8192)
-    assert pl.sched == S.SK_SCHED_SK
+    assert (pl.blk_m, pl.sched, pl.split) == (64, S.SK_SCHED_FIXED_SPLIT, 32)
     # FP8's 128x128x128 tile too
     pl = plan(2048, 1664, 4096, dt="f8e4m3")
     assert (pl.blk_m, pl.blk_k, pl.sched, pl.grid) == (128, 128, S.SK_SCHED_FIXED_SPLIT, 416)

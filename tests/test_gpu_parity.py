@@ -160,7 +160,8 @@ def test_hybrids_on_few_slots(sched, slots, ws):
 
 
 @pytest.mark.parametrize("ab,m,n,k,blk_m,sched", [
-    ("bf16", 1024, 1024, 2048, 64, S.SK_SCHED_SK),              # 256 64x64 tiles, 32 iterations each
+    ("bf16", 1024, 1024, 2048, 64, S.SK_SCHED_FIXED_SPLIT),     # 256 64x64 tiles, 32 iterations each
+    ("bf16", 192, 192, 8192, 64, S.SK_SCHED_SK),                # 9 64x64 tiles: the model's grid
     ("bf16", 2048, 1664, 2048, 128, S.SK_SCHED_FIXED_SPLIT),    # k-aligned split: 2 workgroups per tile
     ("f8e4m3", 2048, 1664, 4096, 128, S.SK_SCHED_FIXED_SPLIT),  # the same with FP8's 128x128x128 tile
     ("bf16", 1024, 1024, 127 * 64, 128, S.SK_SCHED_FIXED_SPLIT),  # I = 127: 8 pieces of 16, the last 15
@@ -172,7 +173,7 @@ def test_default_schedule_refinements(ab, m, n, k, blk_m, sched, ws):
     # the machine's own slot counts
     _, plan = check_case(m, n, k, ab, "f32", dist="int4", ws=ws)
     assert (plan.blk_m, plan.sched) == (blk_m, sched), (plan.blk_m, plan.sched, plan.grid)
-    if blk_m == 128:
+    if sched == S.SK_SCHED_FIXED_SPLIT:
         assert plan.grid == plan.split * plan.tiles and plan.max_peers == plan.split - 1
     if sched == S.SK_SCHED_DP_1TILE_SK:
         assert plan.dp_tiles == plan.grid and plan.sk_tile_end - plan.sk_tile_begin == plan.tiles - plan.grid
