@@ -651,7 +651,11 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
         // size (FP64 sweep: basic SK 47.5, two-tile hybrid 47.8, the rule
         // above 43.7, DP 30.6 TFLOP/s): the paper's two-tile hybrid.
         // the 64x64 tile of the 16-bit and FP8 types: Stream-K only below
-        // kTinySkTiles tiles, data-parallel otherwise (see the tile choice)
+        // kTinySkTiles tiles, data-parallel otherwise (see the tile choice);
+        // FP16/BF16 also up to 1.5 CUs' worth of tiles with kDeepIters
+        // k-iterations per tile.  The refinements of the 16-bit default
+        // (kDeepIters, kMidBig*, kTail*, aligned_split) are described with
+        // their constants.
         const bool half = c.key.ab_type == SK_F16 || c.key.ab_type == SK_BF16;
         const bool single = c.probs.size() == 1;
         int64_t sk_tiles = (c.tile.bm <= 64 && c.key.ab_type != SK_F64) ? kTinySkTiles - 1 : cus;
@@ -664,8 +668,9 @@ sk_status_t plan_call(const Call &c, const sk_config_t *cfg, sk_plan_t *pl) {
             sched = SK_SCHED_SK;
             // a model grid of exactly one workgroup per tile (one problem)
             // is the data-parallel schedule: run the data-parallel kernel;
-            // any other model grid of a 16-bit 128x128 problem gives way to
-            // a k-aligned split that fills half of the slots
+            // any other model grid of a single GEMM gives way to the
+            // k-aligned fixed split when that fills enough of the slots
+            // (128x128, FP16/BF16/FP8: half; 64x64, FP16/BF16: 5/8)
             int f0 = 0;
             if (user_grid == 0 && single && std::min<int64_t>(sk_model(&f0), c.iters) == t) {
                 sched = SK_SCHED_DP;
