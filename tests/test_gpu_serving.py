@@ -81,3 +81,42 @@ def test_admission_respects_budget():
         live += dlt
         peak = max(peak, live)
     assert peak <= 3
+
+
+def test_serving_mixed_tiles_share_slots_per_kernel():
+    # batches of small requests (64x64 tiles) and of large ones (128x128 or
+    # 256x256 tiles) in flight together on two streams: each launch is planned
+    # on its own kernel's share of the resident slots, so no fixup wait runs
+    # into its bound (the run raises SkError(SK_ERR_TIMEOUT) if one does) and
+    # every result equals the same GEMM computed alone
+    pools = {"bf16": int_pool("bf16", 1 << 25, 7)}
+    rng = np.random.default_rng(8)
+    trace, t = [], 0.0
+    for i in range(240):
+        t += rng.exponential(1.0 / 40000.0)
+        if i % 6 == 5:
+            m, n, k = int(rng.integers(8, 17)) * 128, int(rng.integers(8, 17)) * 128, int(rng.integers(8, 33)) * 128
+        else:
+            m, n, k = int(rng.integers(1, 9)) * 64, int(rng.integers(1, 9)) * 64, int(rng.integers(2, 33)) * 128
+        trace.append(W.Request(i, t, m, n, k, "bf16"))
+    reqs = SV.make_requests(trace, pools, seed=9)
+    srv = SV.Server(pools, hbm_budget=4 << 30, out_bytes=2 << 30, streams=2, max_batch=16,
+                    max_batch_flops=2e10)
+    say("serving 240 mixed requests")
+    st = srv.run(reqs, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert st.completed == len(reqs)
+    assert len(srv.slots) >= 2, srv.slots          # launches on more than one kernel
+    ws = R.Workspace("cuda")
+    for r in reqs[::11]:
+        mix = srv.output(r).clone()
+        alone = torch.empty((r.m, r.n), dtype=torch.float32, device="cuda")
+        pool = pools[r.dtype]
+        eb = pool.element_size()
+        d = S.make_desc(r.m, r.n, r.k, pool.data_ptr() + r.a_off * eb, pool.data_ptr() + r.b_off * eb,
+                        alone, ab_type=r.dtype, c_type="f32")
+        st_, pl = S.sk_plan(d, None)
+        ws.ensure(pl.workspace_bytes)
+        S.check(S.sk_gemm(d, None, ws.ptr, ws.nbytes, torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert torch.equal(mix.view(torch.int32), alone.view(torch.int32)), f"request {r.rid}"
