@@ -528,7 +528,7 @@ def grouped_leg(tune: bool = True):
         best = tuner.tune_grouped(descs, "bf16", "grouped512", reps=2)
         out["grouped_tuned"] = grouped_time(best.config(), "autotuned")
         out["grouped_tuned"]["choice"] = {"sched": best.sched, "blk": list(best.blk), "grid": best.grid,
-                                          "threshold": best.threshold, "fixup": best.fixup}
+                                          "threshold": best.threshold, "fixup": best.fixup, "split": best.split}
         out["speedup_tuned_vs_paper_rule"] = round(out["grouped_tuned"]["tflops"] /
                                                    out["grouped_paper_rule"]["tflops"], 3)
     best_g = max(v["tflops"] for k, v in out.items() if k.startswith("grouped_"))

@@ -48,10 +48,11 @@ class Choice:
     threshold: int = 0
     us: float = 0.0
     fixup: str = "auto"
+    split: int = 0          # fixed split (Algorithm 4) or a DP + one-tile SK tail's split
 
     def config(self, **extra) -> S.sk_config_t:
         return S.make_config(sched=self.sched, blk=self.blk, grid=self.grid, threshold=self.threshold,
-                             fixup=self.fixup, **extra)
+                             fixup=self.fixup, split=self.split, **extra)
 
 
 def paper_baseline(ab: str) -> Choice:
@@ -171,13 +172,19 @@ class Tuner:
     @staticmethod
     def candidates(ab: str, slots: Optional[Dict[Tuple[int, int, int], int]] = None) -> List[Choice]:
         """The paper's configuration first, then tile x schedule x grid x
-        hybrid threshold x fixup."""
+        hybrid threshold x fixup, the fixed split (Algorithm 4, the library's
+        s) and DP + one-tile SK with fixed-split tails (the library refuses
+        the plans that do not fit a shape -- grouped calls, tails of more than
+        p / s tiles -- and they are skipped)."""
         out = [paper_baseline(ab)]
         for blk in TILES[ab]:
             p = (slots or {}).get(blk, 256)
             out.append(Choice("dp", blk))
             out.append(Choice("auto", blk))
             out.append(Choice("dp1sk", blk))
+            out.append(Choice("fs", blk))
+            for sp in (2, 4, 8, 16):
+                out.append(Choice("dp1sk", blk, split=sp))
             out.append(Choice("2tsk", blk, threshold=1))
             out.append(Choice("2tsk", blk))
             for fx in ("serial", "spread"):
@@ -214,7 +221,7 @@ class Tuner:
             if i == 0:
                 base_us = us        # the paper's configuration
             if best is None or us < best.us:
-                best = Choice(ch.sched, ch.blk, ch.grid, ch.threshold, us, ch.fixup)
+                best = Choice(ch.sched, ch.blk, ch.grid, ch.threshold, us, ch.fixup, ch.split)
         assert best is not None
         self.table[key] = dict(asdict(best), baseline_us=base_us, baseline=asdict(paper_baseline(ab)))
         return best
@@ -223,7 +230,8 @@ class Tuner:
         e = self.table.get(bucket(ab, m, n, k))
         if not e:
             return None
-        return Choice(e["sched"], tuple(e["blk"]), e["grid"], e["threshold"], e["us"], e.get("fixup", "auto"))
+        return Choice(e["sched"], tuple(e["blk"]), e["grid"], e["threshold"], e["us"], e.get("fixup", "auto"),
+                      e.get("split", 0))
 
     def config_for(self, ab: str, m: int, n: int, k: int) -> S.sk_config_t:
         ch = self.lookup(ab, m, n, k)
