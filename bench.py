@@ -460,7 +460,8 @@ def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0) ->
     return {"gemm": f"{m}x{n}x{k}", "ab": ab, "c": ct, "reps": reps, "ms": round(ms, 4),
             "tflops": round(tf, 1), "pct_peak": round(100 * tf / PEAK_TFLOPS[ab], 2),
             "sched": S.SCHED_NAME.get(pl.sched, pl.sched), "grid": pl.grid,
-            "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}", "flags": flags, "xcd_remap": pl.xcd_remap}
+            "split": pl.split, "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}", "flags": flags,
+            "xcd_remap": pl.xcd_remap}
 
 
 def grouped_leg(tune: bool = True):
