@@ -730,8 +730,9 @@ def main():
         "config": {"workload": "geometry sweep: 2048 GEMMs, m,n,k log-uniform in [128,8192] rounded "
                                "to multiples of 8 (seed 1); FP16 inputs U[-1,1], FP32 accumulate "
                                "and output; alpha=1, beta=0; row-major; library default configuration "
-                               "(basic Stream-K while tiles <= CUs, else data-parallel; 128x128 tiles "
-                               "unless 2 full waves)",
+                               "per problem (tile 64x64, 128x128 or 256x256 by size and depth; "
+                               "data-parallel, k-aligned fixed split, basic Stream-K, or data-parallel "
+                               "waves with a fixed-split tail; counts in 'tiles' and 'schedules')",
                    "problems": len(shapes), "flops_per_step": total_flops,
                    "tiles": tiles, "schedules": kinds},
         "pct_peak": round(100 * value / PEAK_TFLOPS["f16"], 2),
