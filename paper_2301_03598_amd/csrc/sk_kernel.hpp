@@ -886,6 +886,66 @@ __device__ __forceinline__ void fix_phase(bool staged, const char *slots, int p0
     }
 }
 
+// Epilogue of an interior tile with no partial sums to add (32x32 blocks):
+// the fragments pass through the idle MAC-loop LDS buffers so that C is
+// written in whole rows.  Straight from the MFMA layout a store instruction
+// covers 32 rows with 32 bytes each (16 with a 16-bit C), one write request
+// per row; after the transpose a wave's instruction covers 1 KiB of
+// consecutive bytes (512 with a 16-bit C), a few whole 128-byte lines, which
+// makes small-k GEMMs (output-write bound) several times cheaper.  The
+// arithmetic per element is that of store_tile_t: alpha * acc, then put4.
+// One band of 2 x 32 rows (32 rows per wave row) per fragment row i; each
+// padded LDS row (BN floats + 16 bytes) starts 4 banks after the previous
+// one, so the 32 rows of a fragment write land in distinct banks.
+template <class C, int CT>
+__device__ __forceinline__ void store_tile_rows(const Problem &P, int tm, int tn,
+                                                const typename C::Frag (&acc)[C::FM][C::FN], int tid, char *lds0,
+                                                char *lds1) {
+    using Acc = typename C::Acc;
+    constexpr int EB = CBytes<CT>::v;
+    constexpr int G = C::FRAG_N / 4;                  // column groups per fragment
+    constexpr int RS = C::BN * 4 + 16;                // padded LDS row
+    constexpr int Q = C::BN / 4;                      // 16-byte chunks per row
+    constexpr int NCH = C::WGM * C::MT * Q / C::THREADS;   // chunks per thread per band
+    static_assert(C::MT == 32 && C::WGM == 2 && C::MT * RS <= C::STAGE, "a band's half fits one k-tile buffer");
+    static_assert((C::WGM * C::MT * Q) % C::THREADS == 0, "whole chunks per thread");
+    const int lane = tid & 63, wave = tid >> 6, wm = wave / C::WGN, wn = wave % C::WGN;
+    char *const half = wm == 0 ? lds0 : lds1;
+    const int wr = (lane % C::MT) * RS + (wn * C::WTN + 4 * (lane / C::MT)) * 4;
+    const Acc alpha = (Acc)P.alpha, beta = (Acc)P.beta;
+    const bool rd = P.beta != 0.0;
+    static_for<C::FM>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        __syncthreads();                              // LDS free: MAC-loop reads, previous band
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) {
+            // an opaque copy where it is used, as in fix_frag: the copies of
+            // all fragments are not hoisted out of the accumulator registers
+            typename C::Frag f = acc[i][j];
+            asm volatile("" : "+v"(f));
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                f32x4 v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = alpha * f[4 * g + e];
+                *(f32x4 *)(half + wr + (j * C::MT + 8 * g) * 4) = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            const int c = tid + u * C::THREADS;
+            const int br = c / Q, c4 = c % Q;         // band row, chunk in the row
+            const f32x4 v = *(const f32x4 *)((br < C::MT ? lds0 : lds1) + (br % C::MT) * RS + c4 * 16);
+            const int row = tm * C::BM + (br / C::MT) * C::WTM + i * C::MT + br % C::MT;
+            const int col = tn * C::BN + 4 * c4;
+            const Acc a[4] = {v[0], v[1], v[2], v[3]};
+            put4<CT, Acc>((char *)P.C + ((int64_t)row * P.ldc + col) * EB, a, beta, rd);
+        }
+    });
+    __syncthreads();                                  // LDS free for the next unit's loads
+}
+
 // C_tile = alpha * (acc + partials of slots [p0, p1]) + beta * C_tile (C read
 // only when beta != 0), rounded once to the output type.  The accumulators
 // are only read here: each fragment is copied, completed with the peers'
@@ -927,6 +987,15 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
             __builtin_amdgcn_sched_barrier(0);
         });
         return;
+    }
+    // (not for the 64x64 tile: the staging's registers would cost its
+    // Stream-K kernel a wave per SIMD)
+    if constexpr (C::MT == 32 && C::BM >= 128) {
+        if (fast && p0 > p1) {
+            // whole rows through the LDS (the flags are uniform over the workgroup)
+            store_tile_rows<C, CT>(P, tm, tn, acc, tid, lds0, lds1);
+            return;
+        }
     }
     const int rowl = tm * C::BM + wm * C::WTM + (lane % C::MT);
     const int coll = tn * C::BN + wn * C::WTN + 4 * (lane / C::MT);
