@@ -886,21 +886,22 @@ __device__ __forceinline__ void fix_phase(bool staged, const char *slots, int p0
     }
 }
 
-// Epilogue of an interior tile with no partial sums to add (32x32 blocks):
-// the fragments pass through the idle MAC-loop LDS buffers so that C is
-// written in whole rows.  Straight from the MFMA layout a store instruction
-// covers 32 rows with 32 bytes each (16 with a 16-bit C), one write request
-// per row; after the transpose a wave's instruction covers 1 KiB of
-// consecutive bytes (512 with a 16-bit C), a few whole 128-byte lines, which
-// makes small-k GEMMs (output-write bound) several times cheaper.  The
-// arithmetic per element is that of store_tile_t: alpha * acc, then put4.
-// One band of 2 x 32 rows (32 rows per wave row) per fragment row i; each
-// padded LDS row (BN floats + 16 bytes) starts 4 banks after the previous
-// one, so the 32 rows of a fragment write land in distinct banks.
+// Epilogue of a tile with no partial sums to add (32x32 blocks, C rows
+// 16-byte aligned): the fragments pass through the idle MAC-loop LDS buffers
+// so that C is written in whole rows.  Straight from the MFMA layout a store
+// instruction covers 32 rows with 32 bytes each (16 with a 16-bit C), one
+// write request per row; after the transpose a wave's instruction covers
+// 1 KiB of consecutive bytes (512 with a 16-bit C), a few whole 128-byte
+// lines, which makes small-k GEMMs (output-write bound) several times
+// cheaper.  The arithmetic per element is that of store_tile_t: alpha * acc,
+// then + beta * C, rounded once.  One band of 2 x 32 rows (32 rows per wave
+// row) per fragment row i; each padded LDS row (BN floats + 16 bytes) starts
+// 4 banks after the previous one, so the 32 rows of a fragment write land in
+// distinct banks.  Rows and columns past the edge of C are not stored.
 template <class C, int CT>
 __device__ __forceinline__ void store_tile_rows(const Problem &P, int tm, int tn,
                                                 const typename C::Frag (&acc)[C::FM][C::FN], int tid, char *lds0,
-                                                char *lds1) {
+                                                char *lds1, bool interior) {
     using Acc = typename C::Acc;
     constexpr int EB = CBytes<CT>::v;
     constexpr int G = C::FRAG_N / 4;                  // column groups per fragment
@@ -940,7 +941,20 @@ __device__ __forceinline__ void store_tile_rows(const Problem &P, int tm, int tn
             const int row = tm * C::BM + (br / C::MT) * C::WTM + i * C::MT + br % C::MT;
             const int col = tn * C::BN + 4 * c4;
             const Acc a[4] = {v[0], v[1], v[2], v[3]};
-            put4<CT, Acc>((char *)P.C + ((int64_t)row * P.ldc + col) * EB, a, beta, rd);
+            char *const q = (char *)P.C + ((int64_t)row * P.ldc + col) * EB;
+            if (interior || (row < P.m && col + 4 <= P.n)) {
+                put4<CT, Acc>(q, a, beta, rd);
+            } else if (row < P.m) {
+                // the last chunk of a row that ends inside it
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (col + e < P.n) {
+                        Acc w = a[e];
+                        if (rd) w = w + beta * load_c<CT, Acc>(q + e * EB);
+                        put_c<CT, Acc>(q + e * EB, w);
+                    }
+                }
+            }
         }
     });
     __syncthreads();                                  // LDS free for the next unit's loads
@@ -991,9 +1005,10 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
     // (not for the 64x64 tile: the staging's registers would cost its
     // Stream-K kernel a wave per SIMD)
     if constexpr (C::MT == 32 && C::BM >= 128) {
-        if (fast && p0 > p1) {
-            // whole rows through the LDS (the flags are uniform over the workgroup)
-            store_tile_rows<C, CT>(P, tm, tn, acc, tid, lds0, lds1);
+        if (P.c_vec && p0 > p1) {
+            // whole rows through the LDS, edge tiles included (the flags are
+            // uniform over the workgroup)
+            store_tile_rows<C, CT>(P, tm, tn, acc, tid, lds0, lds1, interior);
             return;
         }
     }
