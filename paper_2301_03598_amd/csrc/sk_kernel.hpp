@@ -1002,9 +1002,10 @@ __device__ __forceinline__ void store_tile_t(const Problem &P, int tm, int tn,
         });
         return;
     }
-    // (not for the 64x64 tile: the staging's registers would cost its
-    // Stream-K kernel a wave per SIMD)
-    if constexpr (C::MT == 32 && C::BM >= 128) {
+    // (16-bit inputs only, from the 128x128 tile on: the staging's registers
+    // would cost the 64x64 Stream-K kernel a wave per SIMD, and with it the
+    // FP8 kernels' MAC loops measured 3 % slower at large k)
+    if constexpr (C::MT == 32 && C::BM >= 128 && C::DT != Dt::F8) {
         if (P.c_vec && p0 > p1) {
             // whole rows through the LDS, edge tiles included (the flags are
             // uniform over the workgroup)
