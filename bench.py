@@ -704,6 +704,19 @@ def main():
                 "avg_flops_per_launch": avg_flops, "time_share": round(run.group_ms[kname] / total_ms, 3),
                 "per_kernel_avg_us": {k: round(run.group_ms[k] * 1e3 / (len(run.groups[k]) * run.group_steps), 3)
                                       for k in run.groups}}
+    # the same figures for every kernel symbol: when several carry nearly
+    # equal shares of the sweep's time, which one is dominant can change
+    # from run to run
+    per_kernel = {}
+    for k, ids in run.groups.items():
+        k_ms = run.group_ms[k] / (len(ids) * run.group_steps)
+        k_flops = sum(sweep.flops[i] for i in ids) / len(ids)
+        k_att = sum(sweep.flops[i] / (attainable_tflops(*sweep.shapes[i], 2, 4, PEAK_TFLOPS["f16"]) * 1e12) * 1e3
+                    for i in ids)
+        per_kernel[k] = {"time_share": round(run.group_ms[k] / total_ms, 3),
+                         "frac": round(k_flops / (k_ms * 1e-3) / 1e12 / PEAK_TFLOPS["f16"], 4),
+                         "frac_of_attainable": round(k_att / (k_ms * len(ids)), 4)}
+    roofline["per_kernel"] = per_kernel
 
     ext = None
     total_flops = sweep.total_flops
