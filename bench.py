@@ -5,16 +5,19 @@ Workload (one "step"): the geometry sweep -- 2048 GEMMs with m, n, k drawn
 log-uniformly from [128, 8192] (seed 1, rounded to multiples of 8), FP16
 inputs uniform in [-1, 1], FP32 accumulation and output, alpha = 1,
 beta = 0, row-major -- each run once through sk_gemm with the library's
-default configuration (basic Stream-K while the tiles cannot give every CU
-a workgroup, data-parallel otherwise; 128x128 tiles unless a problem has 8
-full waves of them).  Inputs are resident in HBM before timing starts.
+default configuration (per problem: a 64x64, 128x128 or 256x256 tile by size
+and depth; data-parallel, k-aligned fixed split, basic Stream-K, or
+data-parallel waves with a fixed-split tail).  Inputs are resident in HBM
+before timing starts.
 
 Reported on one JSON line: aggregate TFLOP/s of the step (value), % of the
 FP16 dense MFMA peak, per-GEMM latency p50/p99, the same sweep under the
 data-parallel, basic Stream-K and the paper's two-tile Stream-K + DP hybrid
-schedules (the paper's comparison), the roofline of the dominant kernel
-measured with HIP events on the launch stream, and the CPU oracle timed on a
-bounded sample of the same workload.
+schedules (the paper's comparison), the fixed split and the best of the
+library's data-parallel tiles per problem, the roofline of the dominant
+kernel (and of every other kernel symbol) measured with HIP events on the
+launch stream, and the CPU oracle timed on a bounded sample of the same
+workload.
 
 `--extended` adds the FP64 sweep and the precision set (BF16 and FP8 on
 8192^3, 256x256x65536, 4096x1024x4096).
@@ -424,11 +427,11 @@ def extended():
     return out
 
 
-def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0) -> dict:
+def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0, ldc: int = 0) -> dict:
     """One precision-set style GEMM (N(0,1) operands from seed 2, BF16 output
     for 16-bit and FP8 inputs, FP64 for FP64), default configuration (plus
-    the given SK_FLAG_* bits): 3 warm-up launches, then `reps` timed back to
-    back."""
+    the given SK_FLAG_* bits; C's leading dimension `ldc`, 0 for n): 3
+    warm-up launches, then `reps` timed back to back."""
     import torch
     import workloads as W
     from paper_2301_03598_amd import runtime as R
@@ -440,9 +443,9 @@ def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0) ->
     B = torch.empty(k * n, dtype=W.torch_dtype(ab), device="cuda")
     W.device_fill_(A, "normal", gen)
     W.device_fill_(B, "normal", gen)
-    C = torch.empty(m * n, dtype=W.torch_dtype(ct), device="cuda")
+    C = torch.empty(m * (ldc or n), dtype=W.torch_dtype(ct), device="cuda")
     cfg = S.make_config(flags=flags)
-    d = S.make_desc(m, n, k, A, B, C, ab_type=ab, c_type=ct, a_scale=1.0, b_scale=1.0)
+    d = S.make_desc(m, n, k, A, B, C, ab_type=ab, c_type=ct, ldc=ldc, a_scale=1.0, b_scale=1.0)
     st, pl = S.sk_plan(d, cfg)
     S.check(st, "sk_plan")
     ws = R.Workspace("cuda", pl.workspace_bytes)
@@ -461,7 +464,7 @@ def one_gemm(m: int, n: int, k: int, ab: str, reps: int = 20, flags: int = 0) ->
             "tflops": round(tf, 1), "pct_peak": round(100 * tf / PEAK_TFLOPS[ab], 2),
             "sched": S.SCHED_NAME.get(pl.sched, pl.sched), "grid": pl.grid,
             "split": pl.split, "tile": f"{pl.blk_m}x{pl.blk_n}x{pl.blk_k}", "flags": flags,
-            "xcd_remap": pl.xcd_remap}
+            "xcd_remap": pl.xcd_remap, "ldc": ldc or n}
 
 
 def grouped_leg(tune: bool = True):
@@ -584,6 +587,9 @@ def main():
                          "and print its JSON; for profiling a single kernel")
     ap.add_argument("--gemm-flags", type=int, default=0,
                     help="SK_FLAG_* bits for --gemm (1: no XCD remap, 2: row-major tile order)")
+    ap.add_argument("--gemm-ldc", type=int, default=0,
+                    help="leading dimension of C for --gemm (0: n); rows that are not 16-byte aligned "
+                         "take the epilogue that stores from the MFMA layout")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -593,7 +599,7 @@ def main():
         S.lib()
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         m, n, k = (int(v) for v in args.gemm[:3])
-        print(json.dumps(one_gemm(m, n, k, args.gemm[3], flags=args.gemm_flags)), flush=True)
+        print(json.dumps(one_gemm(m, n, k, args.gemm[3], flags=args.gemm_flags, ldc=args.gemm_ldc)), flush=True)
         return
     if args.copy_calibration:
         import torch
